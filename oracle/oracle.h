@@ -1,0 +1,80 @@
+/*
+ * CPU oracle for sparse TSDF fusion and raycasting — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, double-precision restatement of what the method computes:
+ * the truncated signed distance of Eq. (1), the block-sparse storage with a
+ * dense per-block offset table (Section 4, Fig. 4-5), the projective
+ * measurement of Section 7.1, the Kalman update of Algorithm 3, the
+ * allocation rule of the Fig. 4 caption and the raycast of Section 5.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code with the HIP library.
+ *
+ * Units: distances are stored normalised by the truncation distance delta
+ * (T_hat = T / delta) and variances by delta^2 (P_hat = P / delta^2).  The
+ * sentinel chi is the value 2.0; any |T_hat| > 1 means chi.
+ */
+#ifndef TSDF_ORACLE_H
+#define TSDF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_volume orc_volume;
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EFULL = 3 };
+enum { ORC_NOISE_QUADRATIC = 0, ORC_NOISE_CONSTANT = 1, ORC_NOISE_PER_PIXEL = 2 };
+enum { ORC_HIT = 1, ORC_AMBIGUOUS = 2, ORC_BISECT_INVALID = 4, ORC_MARGINAL = 8 };
+
+typedef struct {
+    int64_t updates;        /* Algorithm 3 executions (voxels with T_k != chi) */
+    int64_t new_blocks;     /* blocks allocated by this frame */
+    int64_t ties;           /* decisions with an FP64 margin below 1e-9 */
+    int64_t visited;        /* voxels whose measurement was evaluated */
+} orc_stats;
+
+orc_volume *orc_create(const int32_t dims[3], double voxel_size, const double origin[3],
+                       double trunc_voxels, double q_hat, int64_t capacity_blocks);
+void orc_destroy(orc_volume *v);
+int64_t orc_block_count(const orc_volume *v);
+
+/* One frame: measurement, allocation and Algorithm 3 for every voxel whose
+ * projective measurement is not chi.  depth is [H][W] metres (<= 0 or
+ * non-finite = no measurement); K = {fx, fy, cx, cy}; pose is camera-to-world
+ * row-major 3x4.  noise_kind selects the measurement variance:
+ *   QUADRATIC: sigma = coeff * D^2, p = sigma^2
+ *   CONSTANT : p_hat = coeff (already in delta^2 units)
+ *   PER_PIXEL: p_hat = phat_px[j*W+i] (delta^2 units)
+ * Returns ORC_EFULL (and stops) when the block store is exhausted. */
+int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const double K[4],
+                  const double pose[12], int32_t noise_kind, double coeff, const double *phat_px,
+                  orc_stats *st);
+
+/* Raycast selected pixels (pixels = n pairs (i, j); NULL = all W*H in row
+ * order).  vertex/normal: n*4 doubles, world frame, w = 1 on a hit, all 0 on
+ * a miss.  flags: ORC_* bits per pixel.  n_threads > 1 splits pixels over
+ * OpenMP threads (results do not depend on it). */
+int orc_raycast(const orc_volume *v, int32_t W, int32_t H, const double K[4], const double pose[12],
+                const int32_t *pixels, int64_t n, double *vertex, double *normal, int32_t *flags,
+                int32_t n_threads);
+
+/* Interpolated distance F at a world point; returns 0 when F is invalid. */
+int orc_sample(const orc_volume *v, const double p[3], double *F);
+
+/* Block store access, in allocation order: keys n*3 (block coordinates),
+ * T and P n*512 in voxel order x + 8y + 64z. */
+int64_t orc_export(const orc_volume *v, int32_t *keys, double *T, double *P, int64_t cap);
+/* Allocate (if needed) block (bx, by, bz) and overwrite its 512 voxels. */
+int orc_set_block(orc_volume *v, const int32_t key[3], const double *T, const double *P);
+
+/* Scalar update rules (normalised units, chi = any |T| > 1). */
+void orc_alg1_step(double *T, double Tk, double w);
+void orc_alg2_step(double *T, double *Wsum, double Tk, double w, double w_max);
+void orc_alg3_step(double *T, double *P, double Tk, double pk, double q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
