@@ -1,0 +1,268 @@
+"""Benchmark: per-frame fusion + raycast of the block-sparse TSDF on one MI355X.
+
+A step is one frame of the synthetic sequence: integrate the depth map
+(pixel preparation, candidate blocks, allocation, Kalman update) and
+raycast the volume from the same pose into vertex and normal maps.  All
+depth maps are generated into HBM before the timed region.
+
+Reported (one JSON line):
+  value           voxel-updates/s = Algorithm 3 executions / GPU time of the
+                  integration kernels (HIP events around each launch)
+  raycast_mpix_s  W*H per second of raycast kernel time (misses count)
+  roofline        the dominant kernel's algorithmic bytes / its average
+                  launch time against the 8 TB/s HBM peak
+  cpu_baseline    the double-precision CPU oracle on a bounded sample of the
+                  same workload, on this host
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "voxel-updates/s + raycast Mpix/s at 1 GPU; % of HBM peak vs FP32 plain form"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_spec(name, frames):
+    from synthetic.configs import config_c1, config_c2, config_c3
+
+    if name == "c1":
+        return config_c1()
+    if name == "c2":
+        return config_c2(n_frames=frames)
+    if name == "c3":
+        return config_c3(n_frames=frames)
+    raise ValueError(name)
+
+
+def generate(spec, n, device="cuda"):
+    from synthetic.configs import sequence_frame
+
+    depths, poses = [], []
+    for k in range(n):
+        d, p = sequence_frame(spec, k % spec.n_frames, device=device)
+        depths.append(d.contiguous())
+        poses.append(p)
+    torch.cuda.synchronize()
+    return depths, poses
+
+
+def fuse_bytes(st, elem, pixels):
+    """Algorithmic bytes of the fusion kernel over the recorded frames.
+
+    Per update in an existing block: read and write T and P (4 * elem);
+    per newly allocated block: write all 512 T and P (2 * 512 * elem), which
+    covers the updates inside it; per pixel per frame: one read of the
+    (depth, variance) pair (8 B); per candidate block: its 4-byte key.
+    """
+    upd_old = st["total_updates"] - st["total_fresh_updates"]
+    return (4 * elem * upd_old + 2 * 512 * elem * st["total_new_blocks"] + 8 * pixels + 4 * st["total_candidates"])
+
+
+def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
+    from paper_1311_7194_amd import Volume
+
+    K = spec.K
+    vol = Volume.from_grid(spec.grid, storage=storage, q_hat=q_hat, max_width=K.width, max_height=K.height)
+    log(f"{spec.name}: volume {vol.nbytes / 2**30:.2f} GiB, generating {steps} frames")
+    depths, poses = generate(spec, max(steps, warmup))
+    vert = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(vert)
+    for k in range(warmup):
+        vol.integrate(depths[k], K, poses[k])
+        vol.raycast(K, poses[k], vert, nrm)
+    torch.cuda.synchronize()
+    vol.reset()
+    vol.set_timing(True)
+    vol.read_timing(reset=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        vol.integrate(depths[k], K, poses[k])
+        vol.raycast(K, poses[k], vert, nrm)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = vol.stats()
+    tm = vol.read_timing()
+    hits = int((vert[..., 3] > 0).sum().item())
+    elem = 2 if storage == 1 else 4
+    pixels = steps * K.width * K.height
+    integ_ms = tm["prep_ms"] + tm["fuse_ms"]
+    res = dict(
+        workload=spec.name, storage="f16" if storage == 1 else "f32", frames=steps,
+        grid=spec.grid.dims[0], voxel_mm=spec.grid.voxel_size * 1e3, width=K.width, height=K.height,
+        updates=st["total_updates"], new_blocks=st["total_new_blocks"], candidates=st["total_candidates"],
+        allocated_blocks=st["allocated_blocks"], status_flags=st["status_flags"],
+        prep_ms=tm["prep_ms"], fuse_ms=tm["fuse_ms"], raycast_ms=tm["raycast_ms"],
+        step_ms=e0.elapsed_time(e1) / steps, wall_s=wall, last_frame_hits=hits,
+        voxel_updates_per_s=st["total_updates"] / (integ_ms * 1e-3),
+        raycast_mpix_s=pixels / (tm["raycast_ms"] * 1e-3) / 1e6,
+    )
+    fb = fuse_bytes(st, elem, pixels)
+    res["fuse_bytes"] = fb
+    res["fuse_gbs"] = fb / (tm["fuse_ms"] * 1e-3) / 1e9
+    res["fuse_avg_us"] = tm["fuse_ms"] * 1e3 / max(tm["fuse_launches"], 1)
+    res["raycast_avg_us"] = tm["raycast_ms"] * 1e3 / max(tm["raycast_launches"], 1)
+    res["prep_avg_us"] = tm["prep_ms"] * 1e3 / max(tm["prep_launches"], 1)
+    # raycast algorithmic bytes counted as its output only (32 B per pixel): a lower bound
+    res["raycast_gbs_output_only"] = 32 * pixels / (tm["raycast_ms"] * 1e-3) / 1e9
+    res["_vol"] = vol
+    return res
+
+
+def roofline_of(res):
+    """Roofline object for the kernel with the larger share of GPU time."""
+    if res["fuse_ms"] >= res["raycast_ms"]:
+        launches = res["frames"]
+        per_launch = res["fuse_bytes"] / launches
+        achieved = res["fuse_gbs"]
+        return dict(kernel="fuse_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=int(per_launch), avg_launch_us=round(res["fuse_avg_us"], 2))
+    achieved = res["raycast_gbs_output_only"]
+    return dict(kernel="raycast_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                bytes_per_launch=32 * res["width"] * res["height"], avg_launch_us=round(res["raycast_avg_us"], 2))
+
+
+def cpu_baseline(spec, frames=2, ray_pixels=2000):
+    """The oracle (as it stands) on the host: `frames` frames of integration
+    and a seeded sample of raycast pixels of the last frame."""
+    import oracle
+    from synthetic.configs import sequence_frame
+
+    oracle.build(force=False)
+    ov = oracle.OracleVolume.from_grid(spec.grid, q_hat=1e-4)
+    K = spec.K
+    upd = 0
+    t_int = 0.0
+    pose = None
+    for k in range(frames):
+        d, pose = sequence_frame(spec, k)
+        t0 = time.perf_counter()
+        st = ov.integrate(d.numpy(), (K.fx, K.fy, K.cx, K.cy), pose)
+        t_int += time.perf_counter() - t0
+        upd += st["updates"]
+    rng = np.random.default_rng(7)
+    pix = np.stack([rng.integers(0, K.width, ray_pixels), rng.integers(0, K.height, ray_pixels)], 1)
+    t0 = time.perf_counter()
+    ov.raycast((K.fx, K.fy, K.cx, K.cy), pose, K.width, K.height, pixels=pix, n_threads=1)
+    t_ray = time.perf_counter() - t0
+    return dict(value=upd / t_int, unit="voxel-updates/s", cores=1, kind="oracle",
+                raycast_mpix_s=ray_pixels / t_ray / 1e6,
+                sample=f"{spec.name}: integration of frames 0-{frames - 1} ({upd} updates, {t_int:.1f} s) and "
+                       f"raycast of {ray_pixels} seeded pixels of frame {frames - 1} ({t_ray:.1f} s), "
+                       f"single thread, host cpu_count={os.cpu_count()}")
+
+
+def compare_storage(a, b):
+    """FP16 volume against the FP32 one run on the same frames (GPU exports)."""
+    from oracle import sorted_blocks
+
+    ka, Ta, Pa = a.export()
+    kb, Tb, Pb = b.export()
+    torch.cuda.synchronize()
+    ka, Ta, Pa = sorted_blocks(ka.cpu().numpy(), Ta.float().cpu().numpy(), Pa.float().cpu().numpy())
+    kb, Tb, Pb = sorted_blocks(kb.cpu().numpy(), Tb.float().cpu().numpy(), Pb.float().cpu().numpy())
+    same_blocks = ka.shape == kb.shape and bool(np.array_equal(ka, kb))
+    out = dict(same_block_set=same_blocks)
+    if same_blocks:
+        live = (np.abs(Ta) <= 1) & (np.abs(Tb) <= 1)
+        dT = np.abs(Ta[live] - Tb[live])
+        rP = np.abs(Pa[live] - Pb[live]) / np.maximum(Pb[live], 1e-30)
+        out.update(max_dT=float(dT.max()), rms_dT=float(np.sqrt((dT ** 2).mean())),
+                   max_rel_dP=float(rP.max()), mean_rel_dP=float(rP.mean()),
+                   chi_mismatch=int(((np.abs(Ta) <= 1) != (np.abs(Tb) <= 1)).sum()))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
+    ap.add_argument("--variants", type=int, default=1, help="also run the 4096^3 hand sequence in FP32 and FP16")
+    ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    import paper_1311_7194_amd as tsdf
+
+    tsdf.lib()  # fails loudly when the HIP library is missing
+    storage = 1 if args.storage == "f16" else 0
+    spec = make_spec(args.config, args.steps)
+    res = run_sequence(spec, storage, args.steps, args.warmup)
+    log(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}))
+    out = {
+        "metric": METRIC,
+        "value": round(res["voxel_updates_per_s"], 1),
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["step_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": res["workload"], "frames": args.steps, "grid": res["grid"],
+                   "voxel_mm": res["voxel_mm"], "frame": f"{res['width']}x{res['height']}",
+                   "storage": res["storage"], "parallelism": "single-gpu"},
+        "raycast_mpix_s": round(res["raycast_mpix_s"], 2),
+        "stage_us_per_frame": {"prep": round(res["prep_avg_us"], 2), "fuse": round(res["fuse_avg_us"], 2),
+                               "raycast": round(res["raycast_avg_us"], 2)},
+        "updates_per_frame": res["updates"] // args.steps,
+        "roofline": roofline_of(res),
+    }
+    variants = []
+    if args.variants and args.config != "c3":
+        spec3 = make_spec("c3", args.variant_steps)
+        r32 = run_sequence(spec3, 0, args.variant_steps, 3)
+        r16 = run_sequence(spec3, 1, args.variant_steps, 3)
+        cmp = compare_storage(r16["_vol"], r32["_vol"])
+        for r in (r32, r16):
+            variants.append({"workload": r["workload"], "storage": r["storage"], "frames": r["frames"],
+                             "voxel_updates_per_s": round(r["voxel_updates_per_s"], 1),
+                             "raycast_mpix_s": round(r["raycast_mpix_s"], 2),
+                             "updates_per_frame": r["updates"] // r["frames"],
+                             "roofline": roofline_of(r)})
+            log(json.dumps({k: v for k, v in r.items() if not k.startswith("_")}))
+        variants[-1]["vs_f32"] = cmp
+        del r32, r16
+    if variants:
+        out["variants"] = variants
+    if args.cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(make_spec(args.config, 2))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * libtsdf — block-sparse TSDF fusion and raycasting on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of "Real-time High Resolution Fusion of Depth Maps on
+ * GPU" (Trifonov, arXiv:1311.7194):
+ *   - Eq. (1): a truncated signed distance, positive outside the surface,
+ *     replaced by the sentinel chi beyond the truncation distance delta;
+ *   - Section 4 and Fig. 4: the field is split into blocks of 8^3 voxels and
+ *     only blocks that store something other than chi take memory;
+ *   - Section 7.1: each frame contributes the projective measurement T_k(x)
+ *     (project x into the depth map, take the distance to the sample there)
+ *     and Algorithm 3 fuses it with a per-voxel Kalman filter (state T,
+ *     variance P, measurement variance p_k, process variance Q);
+ *   - Section 7.2: blocks intersected by the measured surface are allocated,
+ *     other blocks in view are updated only if already allocated;
+ *   - Section 5: raycasting the sparse field yields vertex and normal maps.
+ *
+ * Conventions shared by every entry point
+ *   Pose: camera-to-world, row-major 3x4 [R | t] in double precision
+ *     (x_world = R x_cam + t).  Camera axes x right, y down, z forward.
+ *   Pixels: (i, j) = (column, row), centre at image point (i, j); a voxel
+ *     projects to the pixel with the nearest centre.
+ *   Depth: float32 [height][width], metres along camera z; <= 0, NaN or Inf
+ *     means no measurement.
+ *   Grid: voxel g in [0, dims) has its centre at origin + (g + 0.5) * voxel_size.
+ *   Stored values are normalised: T_hat = T / delta in [-1, 1] and
+ *     P_hat = P / delta^2; chi is stored as T_hat = 2.
+ *   Device pointers ("_dev") are HIP device memory owned by the caller; the
+ *     library never allocates device memory.  Host pointers are read during
+ *     the call only.
+ *   Streams: every call that takes a hipStream_t enqueues its work on that
+ *     stream and returns without synchronising; buffers passed in must stay
+ *     valid until the work completes.  One volume is driven from one stream
+ *     at a time.
+ *   Errors: argument errors return synchronously and enqueue nothing.
+ *     Exhaustion detected on the device (block pool, hash table, per-frame
+ *     candidate list) latches a sticky device flag.  The library does not
+ *     synchronise to look at it: tsdf_query_stats reads it, and once it has
+ *     seen a flag, tsdf_integrate_frame returns TSDF_EFULL until
+ *     tsdf_reset_volume.  No C++ exception crosses this interface.
+ */
+#ifndef TSDF_H
+#define TSDF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSDF_OK = 0,
+    TSDF_EINVAL = 1,   /* bad argument (null, size, non-finite or non-orthonormal pose, ...) */
+    TSDF_ENOMEM = 2,   /* caller buffer smaller than tsdf_volume_bytes reports */
+    TSDF_EFULL = 3,    /* pool, hash or candidate list exhausted (sticky) */
+    TSDF_EHIP = 4,     /* a HIP runtime call failed */
+    TSDF_ESTATE = 5    /* call not valid in the current state */
+} tsdf_status;
+
+typedef enum { TSDF_F32 = 0, TSDF_F16 = 1 } tsdf_storage;
+
+/* Sticky device status bits (tsdf_stats.status_flags). */
+enum { TSDF_FLAG_POOL_FULL = 1u, TSDF_FLAG_HASH_FULL = 2u, TSDF_FLAG_CAND_FULL = 4u };
+
+typedef struct {
+    int32_t dims[3];           /* virtual grid in voxels, each a positive multiple of 8, <= 8192 */
+    double voxel_size;         /* metres */
+    double origin[3];          /* world position of the grid's min corner, metres */
+    double trunc_voxels;       /* delta = trunc_voxels * voxel_size */
+    uint32_t capacity_blocks;  /* block pool size */
+    uint32_t hash_slots;       /* power of two >= 2 * capacity_blocks */
+    int32_t storage;           /* tsdf_storage: T_hat and P_hat as float32 or float16 */
+    double q_hat;              /* process variance Q / delta^2 (Algorithm 3) */
+    int32_t max_width;         /* largest frame the volume will see */
+    int32_t max_height;
+    uint32_t max_candidates;   /* candidate blocks per frame; 0 = capacity_blocks */
+} tsdf_volume_desc;
+
+typedef struct {
+    double fx, fy, cx, cy;     /* pixels */
+    int32_t width, height;
+} tsdf_intrinsics;
+
+typedef enum {
+    TSDF_NOISE_QUADRATIC = 0,  /* sigma = coeff * D^2, p = sigma^2 (Section 7.1) */
+    TSDF_NOISE_CONSTANT = 1,   /* p_hat = coeff, already in delta^2 units */
+    TSDF_NOISE_MLP = 2         /* learned per-pixel variance, quadratic fallback (tsdf_mlp.h) */
+} tsdf_noise_kind;
+
+typedef struct {
+    int32_t kind;              /* tsdf_noise_kind */
+    double coeff;              /* see tsdf_noise_kind; the MLP uses it for its fallback */
+    const void *mlp_params_dev;/* TSDF_NOISE_MLP: packed parameters, see tsdf_mlp.h */
+} tsdf_noise_model;
+
+typedef struct {
+    uint64_t allocated_blocks;    /* blocks in the pool */
+    uint64_t frame_candidates;    /* candidate blocks examined by the last integrate */
+    uint64_t frame_new_blocks;    /* blocks allocated by the last integrate */
+    uint64_t frame_updates;       /* Algorithm 3 executions in the last integrate */
+    uint64_t frame_fresh_updates; /* ... of which in blocks that frame allocated */
+    uint64_t total_updates;       /* totals since creation or reset */
+    uint64_t total_fresh_updates;
+    uint64_t total_candidates;
+    uint64_t total_new_blocks;
+    uint64_t frames;              /* integrate calls since creation or reset */
+    uint32_t status_flags;        /* TSDF_FLAG_* (sticky) */
+    uint32_t reserved;
+} tsdf_stats;
+
+/* Per-stage kernel times from HIP events recorded around each launch while
+ * timing is enabled (pixel preparation, block fusion, raycast). */
+typedef struct {
+    double prep_ms, fuse_ms, raycast_ms;
+    uint64_t prep_launches, fuse_launches, raycast_launches;
+} tsdf_timing;
+
+typedef struct tsdf_volume tsdf_volume;
+
+/* Device bytes a volume needs (pool, hash table, occupancy bitmaps, per-frame
+ * scratch).  Returns TSDF_EINVAL for an invalid description. */
+tsdf_status tsdf_volume_bytes(const tsdf_volume_desc *desc, uint64_t *bytes);
+
+/* Create a volume in the caller's device buffer dev_buf (>= tsdf_volume_bytes,
+ * 256-byte aligned).  Clears the buffer on `stream`.  The host handle is
+ * written to *out and released by tsdf_destroy_volume. */
+tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint64_t bytes,
+                               hipStream_t stream, tsdf_volume **out);
+void tsdf_destroy_volume(tsdf_volume *vol);
+
+/* Empty the volume (all blocks released, counters and sticky flags cleared). */
+tsdf_status tsdf_reset_volume(tsdf_volume *vol, hipStream_t stream);
+
+/* Fuse one depth map (Section 7): allocate every block holding a voxel whose
+ * measurement is not chi (Fig. 4 caption), then apply Algorithm 3 to every
+ * such voxel.  depth_dev: float32 [K->height][K->width] (width <= max_width,
+ * height <= max_height).  pose_c2w: host, 12 doubles.  noise: host. */
+tsdf_status tsdf_integrate_frame(tsdf_volume *vol, const float *depth_dev, const tsdf_intrinsics *K,
+                                 const double pose_c2w[12], const tsdf_noise_model *noise,
+                                 hipStream_t stream);
+
+/* Raycast the volume (Section 5) from pose_c2w into float4 maps
+ * [K->height][K->width][4] (any frame size): vertex (x, y, z, 1) and unit
+ * normal (x, y, z, 1) in world coordinates; both all zero where the ray finds
+ * no front-facing zero crossing or the normal is undefined.  The ray through
+ * each pixel centre is sampled every half voxel from the camera centre; the
+ * first bracket with F > 0 >= F over valid trilinear samples is refined by
+ * bisection; the normal is the central difference of F one voxel apart
+ * along the world axes. */
+tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
+                         float *vertex_dev, float *normal_dev, hipStream_t stream);
+
+/* Counters and sticky flags; synchronises the stream the volume last used. */
+tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out);
+
+/* Enable (1) or disable (0) per-launch event timing.  While enabled every
+ * kernel launch is bracketed by two HIP events on its stream. */
+tsdf_status tsdf_set_timing(tsdf_volume *vol, int32_t enable);
+/* Sum of the recorded kernel times (synchronises on the events); reset != 0
+ * clears the sums. */
+tsdf_status tsdf_read_timing(tsdf_volume *vol, tsdf_timing *out, int32_t reset);
+
+/* Copy out the allocated blocks in pool order: keys_dev int32 [cap][3]
+ * (block coordinates), T_dev and P_dev [cap][512] of the storage type, voxel
+ * order x + 8y + 64z.  *n_out (host) receives the block count; the call
+ * synchronises `stream` to read it.  Copies min(n, cap) blocks. */
+tsdf_status tsdf_export_blocks(tsdf_volume *vol, int32_t *keys_dev, void *T_dev, void *P_dev,
+                               uint64_t cap, uint64_t *n_out, hipStream_t stream);
+
+/* Insert (or overwrite) n blocks: keys_dev int32 [n][3] distinct block
+ * coordinates inside the grid, T_dev/P_dev [n][512] of the storage type. */
+tsdf_status tsdf_import_blocks(tsdf_volume *vol, const int32_t *keys_dev, const void *T_dev,
+                               const void *P_dev, uint64_t n, hipStream_t stream);
+
+const char *tsdf_status_string(tsdf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,10 @@
+"""Block-sparse TSDF fusion and raycasting for AMD Instinct MI355X (gfx950).
+
+The compute path is libtsdf.so (hand-written HIP kernels behind a C ABI,
+``include/tsdf.h``); this package is its thin Python binding over torch
+device tensors.
+"""
+
+from .tsdf import (  # noqa: F401
+    F16, F32, NOISE_CONSTANT, NOISE_MLP, NOISE_QUADRATIC, TsdfError, Volume, lib, LIB_PATH,
+)

@@ -1,0 +1,151 @@
+// Internal layout and kernel interfaces of libtsdf (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "tsdf.h"
+
+namespace tsdf {
+
+constexpr int kBlock = 8;              // voxels per block edge (M)
+constexpr int kBlockVoxels = 512;      // M^3
+constexpr float kChi = 2.0f;           // stored sentinel; any |T_hat| > 1 is chi
+constexpr uint32_t kEmptyKey = 0xffffffffu;
+constexpr uint64_t kEmptyEntry = ~0ull;
+constexpr int kMaxProbes = 512;        // hash probe limit before HASH_FULL
+
+// Device-resident counters and sticky status (one 256-byte line).
+struct DeviceState {
+    uint32_t pool_count;     // blocks handed out (may exceed capacity after overflow)
+    uint32_t status;         // TSDF_FLAG_* bits, sticky
+    uint32_t cand_count;     // unique candidate blocks of the current frame
+    uint32_t new_blocks;     // blocks allocated by the current frame
+    unsigned long long frame_updates;
+    unsigned long long total_updates;
+    unsigned long long frames;
+    unsigned long long frame_fresh_updates;  // updates inside blocks allocated this frame
+    unsigned long long total_fresh_updates;
+    unsigned long long total_candidates;
+    unsigned long long total_new_blocks;
+    uint32_t pad[46];
+};
+static_assert(sizeof(DeviceState) == 256, "state line");
+
+// Pointers into the caller's device buffer.
+struct VolumeView {
+    DeviceState *state;
+    unsigned long long *hash;   // hash_slots entries: (slot << 32) | key, ~0 = empty
+    uint32_t *occupancy;        // one bit per block of the virtual grid
+    uint32_t *cand_bits;        // per-frame candidate dedup bits (all clear between frames)
+    uint32_t *cand_list;        // max_candidates keys
+    float2 *pixmap;             // per pixel (depth or 0, measurement variance p_hat)
+    void *poolT;                // capacity * 512 * elem
+    void *poolP;
+    int32_t dims[3];
+    int32_t nblk[3];
+    double vs, inv_vs;
+    double origin[3];
+    double delta, inv_delta;
+    float q_hat;
+    uint32_t capacity;
+    uint32_t hash_mask;
+    uint32_t max_candidates;
+    int32_t storage;            // TSDF_F32 / TSDF_F16
+};
+
+struct Camera {
+    double R[9];      // row-major camera-to-world rotation
+    double t[3];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+};
+
+struct NoiseParams {
+    int32_t kind;
+    float coeff;
+    const void *mlp;
+};
+
+// Block key: 10 bits per axis.
+__host__ __device__ inline uint32_t pack_key(int bx, int by, int bz)
+{
+    return (uint32_t)bx | ((uint32_t)by << 10) | ((uint32_t)bz << 20);
+}
+__host__ __device__ inline void unpack_key(uint32_t k, int &bx, int &by, int &bz)
+{
+    bx = (int)(k & 1023u);
+    by = (int)((k >> 10) & 1023u);
+    bz = (int)((k >> 20) & 1023u);
+}
+__host__ __device__ inline uint32_t hash_key(uint32_t k)
+{
+    // murmur3 finaliser
+    k ^= k >> 16;
+    k *= 0x85ebca6bu;
+    k ^= k >> 13;
+    k *= 0xc2b2ae35u;
+    k ^= k >> 16;
+    return k;
+}
+__host__ __device__ inline uint64_t block_linear(const VolumeView &v, int bx, int by, int bz)
+{
+    return ((uint64_t)bz * (uint64_t)v.nblk[1] + (uint64_t)by) * (uint64_t)v.nblk[0] + (uint64_t)bx;
+}
+
+// Lookup: slot or -1.
+__device__ inline int32_t hash_find(const VolumeView &v, uint32_t key)
+{
+    uint32_t h = hash_key(key) & v.hash_mask;
+    for (int p = 0; p < kMaxProbes; ++p) {
+        unsigned long long e = v.hash[h];
+        uint32_t k = (uint32_t)(e & 0xffffffffu);
+        if (k == key) return (int32_t)(e >> 32);
+        if (k == kEmptyKey) return -1;
+        h = (h + 1) & v.hash_mask;
+    }
+    return -1;
+}
+
+// Insert a key that no other thread inserts concurrently and that is not in
+// the table.  Returns the new pool slot, or -1 with a sticky flag set.
+__device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
+{
+    uint32_t slot = atomicAdd(&v.state->pool_count, 1u);
+    if (slot >= v.capacity) {
+        atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_POOL_FULL);
+        return -1;
+    }
+    unsigned long long entry = ((unsigned long long)slot << 32) | key;
+    uint32_t h = hash_key(key) & v.hash_mask;
+    for (int p = 0; p < kMaxProbes; ++p) {
+        unsigned long long prev = atomicCAS(&v.hash[h], kEmptyEntry, entry);
+        if (prev == kEmptyEntry) return (int32_t)slot;
+        if ((uint32_t)(prev & 0xffffffffu) == key) return (int32_t)(prev >> 32);
+        h = (h + 1) & v.hash_mask;
+    }
+    atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_HASH_FULL);
+    return -1;
+}
+
+__device__ inline bool occupied(const VolumeView &v, int bx, int by, int bz)
+{
+    uint64_t b = block_linear(v, bx, by, bz);
+    return (v.occupancy[b >> 5] >> (b & 31)) & 1u;
+}
+
+// ---- launchers (return hipError_t of the launch)
+hipError_t launch_clear(const VolumeView &v, uint64_t words_total, uint32_t *base, hipStream_t s);
+hipError_t launch_init_hash(const VolumeView &v, hipStream_t s);
+hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s);
+hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &cam, const NoiseParams &noise,
+                       hipStream_t s);
+hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s);
+hipError_t launch_raycast(const VolumeView &v, const Camera &cam, float4 *vertex, float4 *normal,
+                          hipStream_t s);
+hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
+hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,
+                         hipStream_t s);
+
+}  // namespace tsdf

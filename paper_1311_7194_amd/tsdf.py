@@ -1,0 +1,246 @@
+"""ctypes binding of libtsdf over torch device tensors.
+
+Argument marshalling only: every step of fusion and raycasting runs in the
+HIP kernels of libtsdf.so.  torch provides device memory and streams.
+The library must have been built (``paper_1311_7194_amd.build``); loading
+fails loudly otherwise - there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsdf.so")
+
+F32, F16 = 0, 1
+NOISE_QUADRATIC, NOISE_CONSTANT, NOISE_MLP = 0, 1, 2
+FLAG_POOL_FULL, FLAG_HASH_FULL, FLAG_CAND_FULL = 1, 2, 4
+OK, EINVAL, ENOMEM, EFULL, EHIP, ESTATE = 0, 1, 2, 3, 4, 5
+
+EXPORTED = [
+    "tsdf_volume_bytes", "tsdf_create_volume", "tsdf_destroy_volume", "tsdf_reset_volume",
+    "tsdf_integrate_frame", "tsdf_raycast", "tsdf_query_stats", "tsdf_export_blocks",
+    "tsdf_import_blocks", "tsdf_status_string", "tsdf_set_timing", "tsdf_read_timing",
+]
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("voxel_size", ctypes.c_double),
+                ("origin", ctypes.c_double * 3), ("trunc_voxels", ctypes.c_double),
+                ("capacity_blocks", ctypes.c_uint32), ("hash_slots", ctypes.c_uint32),
+                ("storage", ctypes.c_int32), ("q_hat", ctypes.c_double),
+                ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
+                ("max_candidates", ctypes.c_uint32)]
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class NoiseModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("coeff", ctypes.c_double), ("mlp_params_dev", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("allocated_blocks", ctypes.c_uint64), ("frame_candidates", ctypes.c_uint64),
+                ("frame_new_blocks", ctypes.c_uint64), ("frame_updates", ctypes.c_uint64),
+                ("frame_fresh_updates", ctypes.c_uint64), ("total_updates", ctypes.c_uint64),
+                ("total_fresh_updates", ctypes.c_uint64), ("total_candidates", ctypes.c_uint64),
+                ("total_new_blocks", ctypes.c_uint64), ("frames", ctypes.c_uint64),
+                ("status_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_double), ("fuse_ms", ctypes.c_double), ("raycast_ms", ctypes.c_double),
+                ("prep_launches", ctypes.c_uint64), ("fuse_launches", ctypes.c_uint64),
+                ("raycast_launches", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TsdfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {lib().tsdf_status_string(status).decode()} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1311_7194_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.tsdf_volume_bytes.argtypes = [P, P]
+        L.tsdf_create_volume.argtypes = [P, P, ctypes.c_uint64, P, P]
+        L.tsdf_destroy_volume.argtypes = [P]
+        L.tsdf_destroy_volume.restype = None
+        L.tsdf_reset_volume.argtypes = [P, P]
+        L.tsdf_integrate_frame.argtypes = [P, P, P, P, P, P]
+        L.tsdf_raycast.argtypes = [P, P, P, P, P, P]
+        L.tsdf_query_stats.argtypes = [P, P]
+        L.tsdf_export_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P, P]
+        L.tsdf_import_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P]
+        L.tsdf_set_timing.argtypes = [P, ctypes.c_int32]
+        L.tsdf_read_timing.argtypes = [P, P, ctypes.c_int32]
+        L.tsdf_status_string.argtypes = [ctypes.c_int]
+        L.tsdf_status_string.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("tsdf_destroy_volume", "tsdf_status_string"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise TsdfError(rc, what)
+
+
+def stream_handle(stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_intrinsics(K) -> Intrinsics:
+    """From an object with fx, fy, cx, cy, width, height (or a 6-tuple)."""
+    if hasattr(K, "fx"):
+        return Intrinsics(K.fx, K.fy, K.cx, K.cy, K.width, K.height)
+    fx, fy, cx, cy, w, h = K
+    return Intrinsics(fx, fy, cx, cy, int(w), int(h))
+
+
+def _pose_array(pose) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(pose, np.float64).reshape(12))
+    return p
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Volume:
+    """A block-sparse TSDF volume living in one torch device buffer."""
+
+    def __init__(self, dims: Sequence[int], voxel_size: float, origin: Sequence[float],
+                 trunc_voxels: float = 4.0, capacity_blocks: int = 1 << 16, hash_slots: Optional[int] = None,
+                 storage: int = F32, q_hat: float = 1e-4, max_width: int = 640, max_height: int = 480,
+                 max_candidates: int = 0, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        if hash_slots is None:
+            hash_slots = 1
+            while hash_slots < 2 * capacity_blocks:
+                hash_slots *= 2
+        self.desc = VolumeDesc((ctypes.c_int32 * 3)(*[int(d) for d in dims]), float(voxel_size),
+                               (ctypes.c_double * 3)(*[float(o) for o in origin]), float(trunc_voxels),
+                               int(capacity_blocks), int(hash_slots), int(storage), float(q_hat),
+                               int(max_width), int(max_height), int(max_candidates))
+        nbytes = ctypes.c_uint64(0)
+        _check(lib().tsdf_volume_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)), "tsdf_volume_bytes")
+        self.nbytes = int(nbytes.value)
+        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(lib().tsdf_create_volume(ctypes.byref(self.desc), _ptr(self.buffer), self.nbytes,
+                                        stream_handle(stream), ctypes.byref(self.handle)),
+               "tsdf_create_volume")
+        self.storage = int(storage)
+        self.dims = tuple(int(d) for d in dims)
+        self.voxel_size = float(voxel_size)
+        self.origin = tuple(float(o) for o in origin)
+        self.delta = float(trunc_voxels) * float(voxel_size)
+        self.capacity = int(capacity_blocks)
+
+    @classmethod
+    def from_grid(cls, grid, storage: int = F32, q_hat: float = 1e-4, max_width: int = 640,
+                  max_height: int = 480, **kw):
+        return cls(grid.dims, grid.voxel_size, grid.origin, grid.trunc_voxels, grid.capacity_blocks,
+                   grid.hash_slots, storage, q_hat, max_width, max_height, **kw)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().tsdf_destroy_volume(h)
+            self.handle = None
+
+    @property
+    def elem_dtype(self):
+        return torch.float16 if self.storage == F16 else torch.float32
+
+    def reset(self, stream=None):
+        _check(lib().tsdf_reset_volume(self.handle, stream_handle(stream)), "tsdf_reset_volume")
+
+    def integrate(self, depth: torch.Tensor, K, pose, noise_kind: int = NOISE_QUADRATIC,
+                  coeff: float = 0.0015, mlp_params: Optional[torch.Tensor] = None, stream=None):
+        assert depth.is_cuda and depth.dtype == torch.float32 and depth.is_contiguous()
+        intr = make_intrinsics(K)
+        assert depth.shape == (intr.height, intr.width)
+        p = _pose_array(pose)
+        nm = NoiseModel(int(noise_kind), float(coeff),
+                        ctypes.c_void_p(mlp_params.data_ptr()) if mlp_params is not None else None)
+        _check(lib().tsdf_integrate_frame(self.handle, _ptr(depth), ctypes.byref(intr),
+                                          p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nm),
+                                          stream_handle(stream)), "tsdf_integrate_frame")
+
+    def raycast(self, K, pose, vertex: Optional[torch.Tensor] = None, normal: Optional[torch.Tensor] = None,
+                stream=None):
+        intr = make_intrinsics(K)
+        shape = (intr.height, intr.width, 4)
+        if vertex is None:
+            vertex = torch.empty(shape, dtype=torch.float32, device=self.buffer.device)
+        if normal is None:
+            normal = torch.empty(shape, dtype=torch.float32, device=self.buffer.device)
+        assert vertex.shape == shape and normal.shape == shape
+        assert vertex.is_contiguous() and normal.is_contiguous()
+        p = _pose_array(pose)
+        _check(lib().tsdf_raycast(self.handle, ctypes.byref(intr), p.ctypes.data_as(ctypes.c_void_p),
+                                  _ptr(vertex), _ptr(normal), stream_handle(stream)), "tsdf_raycast")
+        return vertex, normal
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().tsdf_query_stats(self.handle, ctypes.byref(st)), "tsdf_query_stats")
+        return st.as_dict()
+
+    def set_timing(self, enable: bool):
+        _check(lib().tsdf_set_timing(self.handle, 1 if enable else 0), "tsdf_set_timing")
+
+    def read_timing(self, reset: bool = False) -> dict:
+        t = Timing()
+        _check(lib().tsdf_read_timing(self.handle, ctypes.byref(t), 1 if reset else 0), "tsdf_read_timing")
+        return t.as_dict()
+
+    def export(self, stream=None):
+        """(keys [n,3] int32, T [n,512], P [n,512]) device tensors in pool order."""
+        n = ctypes.c_uint64(0)
+        _check(lib().tsdf_export_blocks(self.handle, None, None, None, 0, ctypes.byref(n),
+                                        stream_handle(stream)), "tsdf_export_blocks")
+        m = int(n.value)
+        dev = self.buffer.device
+        keys = torch.empty((max(m, 1), 3), dtype=torch.int32, device=dev)
+        T = torch.empty((max(m, 1), 512), dtype=self.elem_dtype, device=dev)
+        P = torch.empty((max(m, 1), 512), dtype=self.elem_dtype, device=dev)
+        if m:
+            _check(lib().tsdf_export_blocks(self.handle, _ptr(keys), _ptr(T), _ptr(P), m, ctypes.byref(n),
+                                            stream_handle(stream)), "tsdf_export_blocks")
+        return keys[:m], T[:m], P[:m]
+
+    def import_blocks(self, keys: torch.Tensor, T: torch.Tensor, P: torch.Tensor, stream=None):
+        keys = keys.to(device=self.buffer.device, dtype=torch.int32).contiguous()
+        T = T.to(device=self.buffer.device, dtype=self.elem_dtype).contiguous()
+        P = P.to(device=self.buffer.device, dtype=self.elem_dtype).contiguous()
+        n = keys.shape[0]
+        _check(lib().tsdf_import_blocks(self.handle, _ptr(keys), _ptr(T), _ptr(P), n, stream_handle(stream)),
+               "tsdf_import_blocks")

@@ -1,0 +1,97 @@
+"""The C ABI: every declared symbol is exported, host-side validation works.
+
+These tests load libtsdf.so but make no call that reaches the GPU.
+"""
+
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1311_7194_amd.tsdf as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(tsdf_[a-z0-9_]+)\s*\(", src, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        from paper_1311_7194_amd import build
+
+        build.build()
+    return T.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "tsdf_integrate_frame" in names and "tsdf_raycast" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def desc(**kw):
+    d = dict(dims=(256, 256, 256), voxel_size=0.004, origin=(-0.5, -0.5, 0.2), trunc_voxels=4.0,
+             capacity_blocks=1 << 14, hash_slots=1 << 15, storage=0, q_hat=1e-4, max_width=640,
+             max_height=480, max_candidates=0)
+    d.update(kw)
+    return T.VolumeDesc((ctypes.c_int32 * 3)(*d["dims"]), d["voxel_size"], (ctypes.c_double * 3)(*d["origin"]),
+                        d["trunc_voxels"], d["capacity_blocks"], d["hash_slots"], d["storage"], d["q_hat"],
+                        d["max_width"], d["max_height"], d["max_candidates"])
+
+
+def nbytes(lib, dd):
+    out = ctypes.c_uint64(0)
+    rc = lib.tsdf_volume_bytes(ctypes.byref(dd), ctypes.byref(out))
+    return rc, out.value
+
+
+def test_volume_bytes_accounts_for_pool_and_index(lib):
+    rc, b32 = nbytes(lib, desc())
+    assert rc == T.OK
+    rc, b16 = nbytes(lib, desc(storage=1))
+    assert rc == T.OK
+    # pool: 2 arrays x capacity x 512 voxels x element size
+    assert b32 - b16 == 2 * (1 << 14) * 512 * 2
+    assert b32 >= 2 * (1 << 14) * 512 * 4 + 8 * (1 << 15)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(250, 256, 256)),          # not a multiple of 8
+    dict(dims=(16384, 8, 8)),            # beyond the 10-bit block key
+    dict(voxel_size=0.0),
+    dict(voxel_size=float("nan")),
+    dict(trunc_voxels=-1.0),
+    dict(capacity_blocks=0),
+    dict(hash_slots=3 << 14),            # not a power of two
+    dict(hash_slots=1 << 14),            # below twice the capacity
+    dict(storage=7),
+    dict(q_hat=-1e-3),
+    dict(max_width=0),
+])
+def test_invalid_descriptions_rejected(lib, bad):
+    rc, _ = nbytes(lib, desc(**bad))
+    assert rc == T.EINVAL
+
+
+def test_null_arguments_rejected(lib):
+    out = ctypes.c_uint64(0)
+    assert lib.tsdf_volume_bytes(None, ctypes.byref(out)) == T.EINVAL
+    assert lib.tsdf_create_volume(None, None, 0, None, None) == T.EINVAL
+    h = ctypes.c_void_p()
+    dd = desc()
+    assert lib.tsdf_create_volume(ctypes.byref(dd), None, 1 << 30, None, ctypes.byref(h)) == T.EINVAL
+    assert lib.tsdf_integrate_frame(None, None, None, None, None, None) == T.EINVAL
+    assert lib.tsdf_raycast(None, None, None, None, None, None) == T.EINVAL
+    assert lib.tsdf_query_stats(None, None) == T.EINVAL
+    assert lib.tsdf_status_string(T.EFULL).decode().startswith("block pool")

@@ -1,0 +1,100 @@
+"""HIP library against the oracle, element by element (needs an MI355X).
+
+Block sets must be bit-exact; T_hat within 1e-5 (delta units), P_hat within
+1e-5 relative; raycast depth within 1e-3 voxel and normals within 1e-3 rad
+on pixels both hit, with any hit/miss disagreement explained by an oracle
+flag (ambiguous bracket, marginal crossing).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import Intrinsics, look_at
+from synthetic.configs import config_c1, sequence_frame, small_orbit
+from tests.parity import (Kvec, compare_raycast, compare_volumes, gpu_volume_for, oracle_volume_for)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tsdf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1311_7194_amd as m
+
+    m.lib()
+    return m
+
+
+def run_both(spec, frames, q_hat=1e-4, storage=0, noise_kind=oracle.NOISE_QUADRATIC, coeff=0.0015):
+    gv = gpu_volume_for(spec, storage=storage, q_hat=q_hat)
+    ov = oracle_volume_for(spec, q_hat=q_hat)
+    for k in frames:
+        depth, pose = sequence_frame(spec, k)
+        print(f"[parity] {spec.name} frame {k}", flush=True)
+        ost = ov.integrate(depth.numpy(), Kvec(spec.K), pose, noise_kind, coeff)
+        gv.integrate(depth.cuda(), spec.K, pose, noise_kind, coeff)
+        gst = gv.stats()
+        assert gst["frame_updates"] == ost["updates"], (gst, ost)
+        assert gst["frame_new_blocks"] == ost["new_blocks"], (gst, ost)
+        assert gst["status_flags"] == 0
+    return gv, ov
+
+
+def test_c1_single_frame_fusion_and_raycast(tsdf):
+    spec = config_c1()
+    gv, ov = run_both(spec, [0])
+    st = compare_volumes(gv, ov)
+    print("[parity] c1 volume", st, flush=True)
+    depth, pose = sequence_frame(spec, 0)
+    vert, nrm = gv.raycast(spec.K, pose)
+    torch.cuda.synchronize()
+    ovv, onn, ofl = ov.raycast(Kvec(spec.K), pose, spec.K.width, spec.K.height)
+    rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, spec.grid.voxel_size)
+    print("[parity] c1 raycast", rs, flush=True)
+    assert rs["hits"] > 4000
+
+
+def test_orbit_sequence_fusion_and_raycast(tsdf):
+    """Six frames of a reduced orbit (ragged 100x75 frames, dropout, boxes)."""
+    spec = small_orbit(width=100, height=75, n_frames=6, G=256, vs=0.008)
+    gv, ov = run_both(spec, range(6))
+    st = compare_volumes(gv, ov)
+    print("[parity] orbit volume", st, flush=True)
+    assert st["blocks"] > 300
+    depth, pose = sequence_frame(spec, 3)
+    vert, nrm = gv.raycast(spec.K, pose)
+    torch.cuda.synchronize()
+    ovv, onn, ofl = ov.raycast(Kvec(spec.K), pose, spec.K.width, spec.K.height, n_threads=8)
+    rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, spec.grid.voxel_size)
+    print("[parity] orbit raycast", rs, flush=True)
+
+
+def test_constant_variance_zero_q(tsdf):
+    spec = small_orbit(width=64, height=48, n_frames=4, G=128, vs=0.016)
+    gv, ov = run_both(spec, range(4), q_hat=0.0, noise_kind=oracle.NOISE_CONSTANT, coeff=0.05)
+    compare_volumes(gv, ov)
+
+
+def test_raycast_of_imported_oracle_volume(tsdf):
+    """The oracle's volume copied into the GPU: raycasts must agree."""
+    spec = small_orbit(width=96, height=72, n_frames=3, G=256, vs=0.008)
+    ov = oracle_volume_for(spec)
+    for k in range(3):
+        d, p = sequence_frame(spec, k)
+        ov.integrate(d.numpy(), Kvec(spec.K), p)
+    keys, T, P = ov.export()
+    gv = gpu_volume_for(spec)
+    gv.import_blocks(torch.from_numpy(keys), torch.from_numpy(T).float(), torch.from_numpy(P).float())
+    K = Intrinsics(110.0, 110.0, 60.3, 40.7, 121, 83)   # another camera, ragged size
+    pose = look_at((0.9, 0.6, -0.7), (0.0, 0.1, 0.0))
+    vert, nrm = gv.raycast(K, pose)
+    torch.cuda.synchronize()
+    ovv, onn, ofl = ov.raycast(Kvec(K), pose, K.width, K.height, n_threads=8)
+    rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, spec.grid.voxel_size)
+    print("[parity] imported raycast", rs, flush=True)
+    assert rs["hits"] > 1000
