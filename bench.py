@@ -59,6 +59,8 @@ def generate(spec, n, device="cuda"):
         d, p = sequence_frame(spec, k % spec.n_frames, device=device)
         depths.append(d.contiguous())
         poses.append(p)
+        if (k + 1) % 50 == 0:
+            log(f"{spec.name}: generated {k + 1}/{n} frames")
     torch.cuda.synchronize()
     return depths, poses
 

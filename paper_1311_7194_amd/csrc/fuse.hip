@@ -2,9 +2,9 @@
 //
 //   frame_begin  reset the per-frame counters
 //   prep         per pixel: validity, measurement variance, and the blocks
-//                overlapping the pixel's frustum cell over [D - delta, D + delta]
-//                (candidate blocks, deduplicated first in LDS per 16x16 tile,
-//                then across the frame with a bit per virtual block)
+//                that the pixel's frustum cell over [D - delta, D + delta] may
+//                reach (candidate blocks, deduplicated first in LDS per 16x16
+//                tile, then across the frame with a bit per virtual block)
 //   fuse         one wavefront per candidate block: the 512 projective
 //                measurements, a ballot for "any voxel not chi", lookup or
 //                lock-free insertion of the block, then Algorithm 3 on every
@@ -14,23 +14,27 @@
 // when one of its voxels receives something other than chi.  Section 7.2
 // lets blocks in view but off the surface update only when already
 // allocated; with a voxel-exact measurement this is the same set of voxel
-// updates, since such voxels get chi and are not touched.
+// updates, since such voxels get chi and are not touched.  The paper reads
+// the sampled block list back to the CPU for allocation; here allocation
+// stays on the device (atomic pool counter, lock-free hash).
 #include "tsdf_internal.h"
 
 namespace tsdf {
 
-__global__ void frame_begin_kernel(DeviceState *st)
+__global__ void frame_begin_kernel(DeviceState *st, Counters *ctr)
 {
-    st->cand_count = 0;
-    st->new_blocks = 0;
-    st->frame_updates = 0;
-    st->frame_fresh_updates = 0;
-    st->frames += 1;
+    const int t = threadIdx.x;
+    if (t < kCtrLanes)
+        for (int c = 0; c < CTR_N; ++c) ctr->frame[t][c] = 0;
+    if (t == 0) {
+        st->cand_count = 0;
+        st->frames += 1;
+    }
 }
 
 hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s)
 {
-    hipLaunchKernelGGL(frame_begin_kernel, dim3(1), dim3(1), 0, s, v.state);
+    hipLaunchKernelGGL(frame_begin_kernel, dim3(1), dim3(kCtrLanes), 0, s, v.state, v.ctr);
     return hipGetLastError();
 }
 
@@ -39,9 +43,10 @@ hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s)
 constexpr int kTile = 16;             // 16x16 pixels per workgroup
 constexpr int kLdsSet = 2048;         // LDS hash set of block keys
 constexpr int kLdsList = 1024;        // unique keys held for the global pass
+constexpr int kSubRanges = 4;         // depth sub-intervals of a pixel's frustum cell
 
 // Marks `key` as a candidate of this frame; the first marker appends it to
-// the candidate list.  Called by active lanes of one wavefront.
+// the candidate list.  Called by the active lanes of one wavefront.
 __device__ inline void global_candidate(const VolumeView &v, uint32_t key)
 {
     int bx, by, bz;
@@ -65,6 +70,22 @@ __device__ inline void global_candidate(const VolumeView &v, uint32_t key)
             atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
             atomicAnd(&v.cand_bits[b >> 5], ~bit);
         }
+    }
+}
+
+// Single-lane version for keys that did not fit the LDS set.
+__device__ inline void global_candidate_lane(const VolumeView &v, uint32_t key, int bx, int by, int bz)
+{
+    uint64_t b = block_linear(v, bx, by, bz);
+    uint32_t bit = 1u << (b & 31);
+    uint32_t old = atomicOr(&v.cand_bits[b >> 5], bit);
+    if (old & bit) return;
+    uint32_t idx = atomicAdd(&v.state->cand_count, 1u);
+    if (idx < v.max_candidates) {
+        v.cand_list[idx] = key;
+    } else {
+        atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
+        atomicAnd(&v.cand_bits[b >> 5], ~bit);
     }
 }
 
@@ -98,36 +119,41 @@ __global__ __launch_bounds__(256) void prep_kernel(VolumeView v, const float *__
     }
 
     if (valid) {
-        // world box of the frustum cell (pixel square x depth range)
+        // The frustum cell (pixel square x [D - delta, D + delta]) is cut into
+        // kSubRanges depth slices; each slice's world box gives candidate
+        // blocks (those whose voxel centres the box may contain).
         const double z0 = fmax((double)D - v.delta, 0.0), z1 = (double)D + v.delta;
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        const double ul = (i - 0.5 - cam.cx) / cam.fx, uh = (i + 0.5 - cam.cx) / cam.fx;
+        const double vl = (j - 0.5 - cam.cy) / cam.fy, vh = (j + 0.5 - cam.cy) / cam.fy;
+        const double pad = 0.01 * v.vs;
+        for (int sr = 0; sr < kSubRanges; ++sr) {
+            const double za = z0 + (z1 - z0) * sr / kSubRanges;
+            const double zb = (sr == kSubRanges - 1) ? z1 : z0 + (z1 - z0) * (sr + 1) / kSubRanges;
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double u = i + ((k & 1) ? 0.5 : -0.5);
-            const double w = j + ((k & 2) ? 0.5 : -0.5);
-            const double z = (k & 4) ? z1 : z0;
-            const double xc = (u - cam.cx) / cam.fx * z, yc = (w - cam.cy) / cam.fy * z;
+            for (int k = 0; k < 8; ++k) {
+                const double z = (k & 4) ? zb : za;
+                const double xc = ((k & 1) ? uh : ul) * z, yc = ((k & 2) ? vh : vl) * z;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double xw = cam.R[3 * a] * xc + cam.R[3 * a + 1] * yc + cam.R[3 * a + 2] * z + cam.t[a];
+                    lo[a] = fmin(lo[a], xw);
+                    hi[a] = fmax(hi[a], xw);
+                }
+            }
+            int b0[3], b1[3];
+            bool empty = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double xw = cam.R[3 * a] * xc + cam.R[3 * a + 1] * yc + cam.R[3 * a + 2] * z + cam.t[a];
-                lo[a] = fmin(lo[a], xw);
-                hi[a] = fmax(hi[a], xw);
+                double g0 = ceil((lo[a] - pad - v.origin[a]) * v.inv_vs - 0.5);
+                double g1 = floor((hi[a] + pad - v.origin[a]) * v.inv_vs - 0.5);
+                g0 = fmax(g0, 0.0);
+                g1 = fmin(g1, (double)(v.dims[a] - 1));
+                empty |= !(g0 <= g1);
+                b0[a] = empty ? 0 : (int)g0 >> 3;
+                b1[a] = empty ? -1 : (int)g1 >> 3;
             }
-        }
-        const double pad = 0.01 * v.vs;
-        int b0[3], b1[3];
-        bool empty = false;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double g0 = ceil((lo[a] - pad - v.origin[a]) * v.inv_vs - 0.5);
-            double g1 = floor((hi[a] + pad - v.origin[a]) * v.inv_vs - 0.5);
-            g0 = fmax(g0, 0.0);
-            g1 = fmin(g1, (double)(v.dims[a] - 1));
-            empty |= g0 > g1;
-            b0[a] = (int)g0 >> 3;
-            b1[a] = (int)g1 >> 3;
-        }
-        if (!empty) {
+            if (empty) continue;
             for (int bz = b0[2]; bz <= b1[2]; ++bz)
                 for (int by = b0[1]; by <= b1[1]; ++by)
                     for (int bx = b0[0]; bx <= b1[0]; ++bx) {
@@ -151,21 +177,7 @@ __global__ __launch_bounds__(256) void prep_kernel(VolumeView v, const float *__
                             h = (h + 1) & (kLdsSet - 1);
                         }
                         // LDS set or list exhausted: go straight to the frame-wide dedup
-                        if (!placed) {
-                            // single-lane path: emulate with a one-lane wave call
-                            uint64_t b = block_linear(v, bx, by, bz);
-                            uint32_t bit = 1u << (b & 31);
-                            uint32_t old = atomicOr(&v.cand_bits[b >> 5], bit);
-                            if (!(old & bit)) {
-                                uint32_t idx = atomicAdd(&v.state->cand_count, 1u);
-                                if (idx < v.max_candidates) {
-                                    v.cand_list[idx] = key;
-                                } else {
-                                    atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
-                                    atomicAnd(&v.cand_bits[b >> 5], ~bit);
-                                }
-                            }
-                        }
+                        if (!placed) global_candidate_lane(v, key, bx, by, bz);
                     }
         }
     }
@@ -184,30 +196,42 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
 
 // ---------------------------------------------------------------- fuse
 
-// Projective measurement of one voxel given the lane-constant partial sums
-// of x_c = R^T (x - t).  The operation order repeats the definition exactly
-// (no contraction), so the decisions (nearest pixel, |s| <= delta) are the
-// defined double-precision ones bit for bit.
-struct LaneGeom {
-    double ax, ay, az;   // R[0][k]*dx + R[1][k]*dy for k = x, y, z
+// Camera parameters in float for the pixel-index filter.
+struct CamF {
+    float fx, fy, cx, cy;
 };
 
-__device__ __forceinline__ bool measure_voxel(const VolumeView &v, const Camera &cam, const LaneGeom &g, int gz,
-                                              const float2 *__restrict__ pixmap, float &Tk, float &pk)
+// Projective measurement of one voxel (Section 7.1).  x_c, y_c, z_c and
+// s = D - z_c are the defined double-precision values bit for bit (same
+// operations, same order, no contraction).  The nearest-pixel index is first
+// found in float; when the float value lies within its proven error bound
+// of a rounding boundary the defined double expression decides instead, so
+// the index always equals the defined one.
+__device__ __forceinline__ bool measure_voxel(const VolumeView &v, const Camera &cam, const CamF &cf, double xc,
+                                              double yc, double zc, const float2 *__restrict__ pixmap, float &Tk,
+                                              float &pk)
 {
 #pragma clang fp contract(off)
-    const double pz = v.origin[2] + ((double)gz + 0.5) * v.vs;
-    const double dz = pz - cam.t[2];
-    const double xc = g.ax + cam.R[6] * dz;
-    const double yc = g.ay + cam.R[7] * dz;
-    const double zc = g.az + cam.R[8] * dz;
     if (!(zc > 0.0)) return false;
-    const double u = cam.fx * xc / zc + cam.cx;
-    const double w = cam.fy * yc / zc + cam.cy;
-    const double fu = floor(u + 0.5);
-    const double fw = floor(w + 0.5);
-    if (!(fu >= 0.0 && fu < (double)cam.width && fw >= 0.0 && fw < (double)cam.height)) return false;
-    const float2 pm = pixmap[(size_t)(int)fw * cam.width + (int)fu];
+    const float xf = (float)xc, yf = (float)yc, zf = (float)zc;
+    const float rz = __builtin_amdgcn_rcpf(zf);
+    const float au = cf.fx * xf * rz, av = cf.fy * yf * rz;
+    const float uf = au + cf.cx, vf = av + cf.cy;
+    float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
+    // |u_float - u_exact| <= 8.3e-7 |fx x/z| + 6e-8 (|cx| + |u|); 2e-6 doubles it
+    const float eu = 2e-6f * (fabsf(au) + fabsf(cf.cx) + fabsf(uf)) + 1e-6f;
+    const float ev = 2e-6f * (fabsf(av) + fabsf(cf.cy) + fabsf(vf)) + 1e-6f;
+    const float du = uf + 0.5f - fu, dv = vf + 0.5f - fv;
+    if (!(du > eu && du < 1.0f - eu && dv > ev && dv < 1.0f - ev)) {
+        const double u = cam.fx * xc / zc + cam.cx;
+        const double w = cam.fy * yc / zc + cam.cy;
+        const double fu64 = floor(u + 0.5), fw64 = floor(w + 0.5);
+        if (!(fu64 >= 0.0 && fu64 < (double)cam.width && fw64 >= 0.0 && fw64 < (double)cam.height)) return false;
+        fu = (float)fu64;
+        fv = (float)fw64;
+    }
+    if (!(fu >= 0.0f && fu < (float)cam.width && fv >= 0.0f && fv < (float)cam.height)) return false;
+    const float2 pm = pixmap[(size_t)(int)fv * cam.width + (int)fu];
     if (!(pm.x > 0.0f)) return false;
     const double s = (double)pm.x - zc;
     if (!(fabs(s) <= v.delta)) return false;
@@ -256,29 +280,42 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
     const float2 *__restrict__ pixmap = v.pixmap;
     S *__restrict__ poolT = (S *)v.poolT;
     S *__restrict__ poolP = (S *)v.poolP;
+    const CamF cf{(float)cam.fx, (float)cam.fy, (float)cam.cx, (float)cam.cy};
+    uint32_t acc_upd = 0, acc_fresh = 0, acc_new = 0;
 
     for (uint32_t c = wave; c < ncand; c += nwaves) {
         const uint32_t key = v.cand_list[c];
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
-        LaneGeom g;
+        // x_c = R^T (x - t) = (R00 dx + R10 dy) + R20 dz: the bracket is the
+        // lane's (x, y) part, the last term varies with z
+        double ax, ay, az;
         {
 #pragma clang fp contract(off)
             const double px = v.origin[0] + ((double)(bx * 8 + lx) + 0.5) * v.vs;
             const double py = v.origin[1] + ((double)(by * 8 + ly) + 0.5) * v.vs;
             const double dx = px - cam.t[0];
             const double dy = py - cam.t[1];
-            g.ax = cam.R[0] * dx + cam.R[3] * dy;
-            g.ay = cam.R[1] * dx + cam.R[4] * dy;
-            g.az = cam.R[2] * dx + cam.R[5] * dy;
+            ax = cam.R[0] * dx + cam.R[3] * dy;
+            ay = cam.R[1] * dx + cam.R[4] * dy;
+            az = cam.R[2] * dx + cam.R[5] * dy;
         }
         float Tk[8], pk[8];
         uint32_t vmask = 0;
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
+            double xc, yc, zc;
+            {
+#pragma clang fp contract(off)
+                const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
+                const double dz = pz - cam.t[2];
+                xc = ax + cam.R[6] * dz;
+                yc = ay + cam.R[7] * dz;
+                zc = az + cam.R[8] * dz;
+            }
             Tk[z] = kChi;
             pk[z] = 0.0f;
-            if (measure_voxel(v, cam, g, bz * 8 + z, pixmap, Tk[z], pk[z])) vmask |= 1u << z;
+            if (measure_voxel(v, cam, cf, xc, yc, zc, pixmap, Tk[z], pk[z])) vmask |= 1u << z;
         }
         if (lane == 0) {
             uint64_t b = block_linear(v, bx, by, bz);
@@ -297,8 +334,6 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
                     fresh = 1;
                     uint64_t b = block_linear(v, bx, by, bz);
                     atomicOr(&v.occupancy[b >> 5], 1u << (b & 31));
-                    atomicAdd(&v.state->new_blocks, 1u);
-                    atomicAdd(&v.state->total_new_blocks, 1ull);
                 }
             }
         }
@@ -327,18 +362,25 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
                 }
             }
         }
-        // count Algorithm 3 executions: wave sum of popcounts
-        uint32_t cnt = __popc(vmask);
+        const uint32_t cnt = __popc(vmask);
+        acc_upd += cnt;
+        acc_fresh += fresh ? cnt : 0u;
+        acc_new += (uint32_t)fresh;   // same value in every lane after the broadcast
+    }
+    // wave totals (acc_new is identical in every lane: count it once)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0) {
-            atomicAdd(&v.state->frame_updates, (unsigned long long)cnt);
-            atomicAdd(&v.state->total_updates, (unsigned long long)cnt);
-            if (fresh) {
-                atomicAdd(&v.state->frame_fresh_updates, (unsigned long long)cnt);
-                atomicAdd(&v.state->total_fresh_updates, (unsigned long long)cnt);
-            }
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+        acc_upd += __shfl_xor(acc_upd, off);
+        acc_fresh += __shfl_xor(acc_fresh, off);
+    }
+    if (lane == 0 && (acc_upd | acc_new)) {
+        const int l = wave & (kCtrLanes - 1);
+        atomicAdd(&v.ctr->frame[l][CTR_UPDATES], (unsigned long long)acc_upd);
+        atomicAdd(&v.ctr->total[l][CTR_UPDATES], (unsigned long long)acc_upd);
+        atomicAdd(&v.ctr->frame[l][CTR_FRESH], (unsigned long long)acc_fresh);
+        atomicAdd(&v.ctr->total[l][CTR_FRESH], (unsigned long long)acc_fresh);
+        atomicAdd(&v.ctr->frame[l][CTR_NEW], (unsigned long long)acc_new);
+        atomicAdd(&v.ctr->total[l][CTR_NEW], (unsigned long long)acc_new);
     }
 }
 

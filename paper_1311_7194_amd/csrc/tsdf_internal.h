@@ -16,27 +16,34 @@ constexpr uint32_t kEmptyKey = 0xffffffffu;
 constexpr uint64_t kEmptyEntry = ~0ull;
 constexpr int kMaxProbes = 512;        // hash probe limit before HASH_FULL
 
-// Device-resident counters and sticky status (one 256-byte line).
+// Device-resident state and sticky status (one 256-byte line).
 struct DeviceState {
     uint32_t pool_count;     // blocks handed out (may exceed capacity after overflow)
     uint32_t status;         // TSDF_FLAG_* bits, sticky
     uint32_t cand_count;     // unique candidate blocks of the current frame
-    uint32_t new_blocks;     // blocks allocated by the current frame
-    unsigned long long frame_updates;
-    unsigned long long total_updates;
+    uint32_t near_stamp;     // raycast call id whose range pass met a block at the camera plane
     unsigned long long frames;
-    unsigned long long frame_fresh_updates;  // updates inside blocks allocated this frame
-    unsigned long long total_fresh_updates;
     unsigned long long total_candidates;
-    unsigned long long total_new_blocks;
-    uint32_t pad[46];
+    uint32_t pad[56];
 };
 static_assert(sizeof(DeviceState) == 256, "state line");
+
+// Event counters, spread over kCtrLanes addresses so that thousands of
+// wavefronts do not serialise on one atomic; the host sums the lanes.
+constexpr int kCtrLanes = 256;
+enum { CTR_UPDATES = 0, CTR_FRESH = 1, CTR_NEW = 2, CTR_N = 4 };
+struct Counters {
+    unsigned long long frame[kCtrLanes][CTR_N];
+    unsigned long long total[kCtrLanes][CTR_N];
+};
 
 // Pointers into the caller's device buffer.
 struct VolumeView {
     DeviceState *state;
+    Counters *ctr;
     unsigned long long *hash;   // hash_slots entries: (slot << 32) | key, ~0 = empty
+    uint32_t *pool_keys;        // capacity entries: key of the block in each pool slot
+    uint32_t *tile_range;       // raycast: per 8x8 pixel tile (min depth bits, max depth bits)
     uint32_t *occupancy;        // one bit per block of the virtual grid
     uint32_t *cand_bits;        // per-frame candidate dedup bits (all clear between frames)
     uint32_t *cand_list;        // max_candidates keys
@@ -53,6 +60,7 @@ struct VolumeView {
     uint32_t hash_mask;
     uint32_t max_candidates;
     int32_t storage;            // TSDF_F32 / TSDF_F16
+    int32_t max_width, max_height;
 };
 
 struct Camera {
@@ -118,6 +126,7 @@ __device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
         return -1;
     }
     unsigned long long entry = ((unsigned long long)slot << 32) | key;
+    v.pool_keys[slot] = key;
     uint32_t h = hash_key(key) & v.hash_mask;
     for (int p = 0; p < kMaxProbes; ++p) {
         unsigned long long prev = atomicCAS(&v.hash[h], kEmptyEntry, entry);
@@ -142,7 +151,7 @@ hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s);
 hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &cam, const NoiseParams &noise,
                        hipStream_t s);
 hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s);
-hipError_t launch_raycast(const VolumeView &v, const Camera &cam, float4 *vertex, float4 *normal,
+hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp, float4 *vertex, float4 *normal,
                           hipStream_t s);
 hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
 hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,

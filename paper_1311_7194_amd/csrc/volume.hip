@@ -106,8 +106,8 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // ------------------------------------------------------------ layout
 
 struct Layout {
-    uint64_t state, hash, occupancy, cand_bits, cand_list, pixmap, poolT, poolP, total;
-    uint64_t bitmap_words;
+    uint64_t state, ctr, hash, occupancy, cand_bits, cand_list, pixmap, pool_keys, tile_range, poolT, poolP, total;
+    uint64_t bitmap_words, tile_words;
 };
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -141,6 +141,8 @@ static Layout layout_of(const tsdf_volume_desc *d)
     uint64_t off = 0;
     L.state = off;
     off = align256(off + sizeof(DeviceState));
+    L.ctr = off;
+    off = align256(off + sizeof(Counters));
     L.hash = off;
     off = align256(off + 8ull * d->hash_slots);
     L.occupancy = off;
@@ -151,6 +153,11 @@ static Layout layout_of(const tsdf_volume_desc *d)
     off = align256(off + 4ull * maxc);
     L.pixmap = off;
     off = align256(off + 8ull * (uint64_t)d->max_width * (uint64_t)d->max_height);
+    L.pool_keys = off;
+    off = align256(off + 4ull * d->capacity_blocks);
+    L.tile_words = (uint64_t)((d->max_width + 7) / 8) * (uint64_t)((d->max_height + 7) / 8);
+    L.tile_range = off;
+    off = align256(off + 8ull * L.tile_words);
     L.poolT = off;
     off = align256(off + elem * kBlockVoxels * (uint64_t)d->capacity_blocks);
     L.poolP = off;
@@ -177,6 +184,7 @@ struct tsdf_volume {
     uint8_t *base;
     hipStream_t last_stream;
     uint32_t host_flags;   // sticky flags seen by the last tsdf_query_stats
+    uint32_t raycast_stamp;
     bool timing;
     std::vector<EventPair> pending;   // recorded, not yet read
     std::vector<hipEvent_t> spare;    // events ready for reuse
@@ -274,6 +282,10 @@ static tsdf_status clear_volume(tsdf_volume *v, hipStream_t s)
 {
     const Layout &L = v->layout;
     hipError_t e = fill_u32((uint32_t *)(v->base + L.state), sizeof(DeviceState) / 4, 0u, s);
+    if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.ctr), sizeof(Counters) / 4, 0u, s);
+    // tile ranges: [0, n) min depths (+inf), [n, 2n) max depths (0)
+    if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.tile_range), L.tile_words, 0x7f800000u, s);
+    if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.tile_range) + L.tile_words, L.tile_words, 0u, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.hash), 2ull * v->desc.hash_slots, 0xffffffffu, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.occupancy), L.bitmap_words, 0u, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.cand_bits), L.bitmap_words, 0u, s);
@@ -325,6 +337,12 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     }
     VolumeView &w = v->view;
     w.state = (DeviceState *)(v->base + L.state);
+    w.ctr = (Counters *)(v->base + L.ctr);
+    w.pool_keys = (uint32_t *)(v->base + L.pool_keys);
+    w.tile_range = (uint32_t *)(v->base + L.tile_range);
+    w.max_width = desc->max_width;
+    w.max_height = desc->max_height;
+    v->raycast_stamp = 0;
     w.hash = (unsigned long long *)(v->base + L.hash);
     w.occupancy = (uint32_t *)(v->base + L.occupancy);
     w.cand_bits = (uint32_t *)(v->base + L.cand_bits);
@@ -400,11 +418,13 @@ tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const doubl
                          float *normal_dev, hipStream_t stream)
 {
     if (!vol || !valid_intrinsics(K) || !valid_pose(pose_c2w) || !vertex_dev || !normal_dev) return TSDF_EINVAL;
+    if (K->width > vol->desc.max_width || K->height > vol->desc.max_height) return TSDF_EINVAL;
     Camera cam = make_camera(K, pose_c2w);
     vol->last_stream = stream;
     const VolumeView &w = vol->view;
+    const uint32_t stamp = ++vol->raycast_stamp == 0 ? ++vol->raycast_stamp : vol->raycast_stamp;
     return hip_status(timed(vol, STAGE_RAYCAST, stream, [&] {
-        return launch_raycast(w, cam, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
+        return launch_raycast(w, cam, stamp, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
     }));
 }
 
@@ -412,18 +432,31 @@ tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out)
 {
     if (!vol || !out) return TSDF_EINVAL;
     DeviceState st;
+    Counters *ctr = new (std::nothrow) Counters;
+    if (!ctr) return TSDF_ENOMEM;
     hipError_t e = hipMemcpyAsync(&st, vol->view.state, sizeof(st), hipMemcpyDeviceToHost, vol->last_stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctr, vol->view.ctr, sizeof(Counters), hipMemcpyDeviceToHost, vol->last_stream);
     if (e == hipSuccess) e = hipStreamSynchronize(vol->last_stream);
-    if (e != hipSuccess) return TSDF_EHIP;
+    if (e != hipSuccess) {
+        delete ctr;
+        return TSDF_EHIP;
+    }
+    uint64_t fr[CTR_N] = {0, 0, 0, 0}, tot[CTR_N] = {0, 0, 0, 0};
+    for (int l = 0; l < kCtrLanes; ++l)
+        for (int c = 0; c < CTR_N; ++c) {
+            fr[c] += ctr->frame[l][c];
+            tot[c] += ctr->total[l][c];
+        }
+    delete ctr;
     out->allocated_blocks = st.pool_count < vol->desc.capacity_blocks ? st.pool_count : vol->desc.capacity_blocks;
     out->frame_candidates = st.cand_count;
-    out->frame_new_blocks = st.new_blocks;
-    out->frame_updates = st.frame_updates;
-    out->frame_fresh_updates = st.frame_fresh_updates;
-    out->total_updates = st.total_updates;
-    out->total_fresh_updates = st.total_fresh_updates;
+    out->frame_new_blocks = fr[CTR_NEW];
+    out->frame_updates = fr[CTR_UPDATES];
+    out->frame_fresh_updates = fr[CTR_FRESH];
+    out->total_updates = tot[CTR_UPDATES];
+    out->total_fresh_updates = tot[CTR_FRESH];
     out->total_candidates = st.total_candidates;
-    out->total_new_blocks = st.total_new_blocks;
+    out->total_new_blocks = tot[CTR_NEW];
     out->frames = st.frames;
     out->status_flags = st.status;
     out->reserved = 0;

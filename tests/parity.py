@@ -80,7 +80,7 @@ def compare_raycast(gv, gn, ov, on, oflags, pose, voxel, pixels=None):
     return stats
 
 
-def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None):
+def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None, max_wh=None):
     from paper_1311_7194_amd import Volume
 
     g = spec.grid
@@ -88,8 +88,8 @@ def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None):
     hs = 1
     while hs < 2 * cap:
         hs *= 2
-    return Volume(g.dims, g.voxel_size, g.origin, g.trunc_voxels, cap, hs, storage, q_hat,
-                  spec.K.width, spec.K.height)
+    mw, mh = max_wh or (spec.K.width, spec.K.height)
+    return Volume(g.dims, g.voxel_size, g.origin, g.trunc_voxels, cap, hs, storage, q_hat, mw, mh)
 
 
 def oracle_volume_for(spec, q_hat=1e-4, capacity=None):

@@ -88,7 +88,7 @@ def test_raycast_of_imported_oracle_volume(tsdf):
         d, p = sequence_frame(spec, k)
         ov.integrate(d.numpy(), Kvec(spec.K), p)
     keys, T, P = ov.export()
-    gv = gpu_volume_for(spec)
+    gv = gpu_volume_for(spec, max_wh=(128, 96))
     gv.import_blocks(torch.from_numpy(keys), torch.from_numpy(T).float(), torch.from_numpy(P).float())
     K = Intrinsics(110.0, 110.0, 60.3, 40.7, 121, 83)   # another camera, ragged size
     pose = look_at((0.9, 0.6, -0.7), (0.0, 0.1, 0.0))
