@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "oracle.c")]
+_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c")]
 
 HIT, AMBIGUOUS, BISECT_INVALID, MARGINAL = 1, 2, 4, 8
 NOISE_QUADRATIC, NOISE_CONSTANT, NOISE_PER_PIXEL = 0, 1, 2
@@ -74,6 +74,13 @@ def lib():
         for name in ("orc_alg1_step",):
             getattr(L, name).argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.orc_alg2_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_mlp_param_count.restype = ctypes.c_int
+        L.orc_bf16.restype = ctypes.c_double
+        L.orc_bf16.argtypes = [ctypes.c_double]
+        L.orc_mlp_features.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P]
+        L.orc_mlp_forward.argtypes = [P, P, ctypes.c_int64, P]
+        L.orc_mlp_loss_grad.restype = ctypes.c_double
+        L.orc_mlp_loss_grad.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int32]
         L.orc_alg3_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         _lib = L
     return _lib
@@ -193,6 +200,43 @@ def alg3_step(T: float, P: float, Tk: float, pk: float, q: float):
     p = np.array([P], np.float64)
     lib().orc_alg3_step(_ptr(t), _ptr(p), float(Tk), float(pk), float(q))
     return float(t[0]), float(p[0])
+
+
+MLP_PARAMS = 1249
+
+
+def bf16(x) -> np.ndarray:
+    """bfloat16 round-to-nearest-even of float32(x), element-wise (via the oracle)."""
+    a = np.asarray(x, np.float64)
+    f = lib().orc_bf16
+    return np.vectorize(f, otypes=[np.float64])(a) if a.ndim else np.float64(f(float(a)))
+
+
+def mlp_features(depth, K):
+    """Features [H*W, 4] and validity [H*W] of a depth map (see mlp.c)."""
+    d = np.ascontiguousarray(np.asarray(depth, np.float32))
+    H, W = d.shape
+    feat = np.zeros((H * W, 4))
+    valid = np.zeros(H * W, np.int32)
+    lib().orc_mlp_features(_ptr(d), W, H, _ptr(_f64(K[:4])), _ptr(feat), _ptr(valid))
+    return feat, valid.astype(bool)
+
+
+def mlp_forward(params, x):
+    p = _f64(params)
+    xx = _f64(x).reshape(-1, 4)
+    out = np.zeros(xx.shape[0])
+    lib().orc_mlp_forward(_ptr(p), _ptr(xx), xx.shape[0], _ptr(out))
+    return out
+
+
+def mlp_loss_grad(params, x, r, round_bf16: bool = True):
+    p = _f64(params)
+    xx = _f64(x).reshape(-1, 4)
+    rr = _f64(r).reshape(-1)
+    g = np.zeros(MLP_PARAMS)
+    loss = lib().orc_mlp_loss_grad(_ptr(p), _ptr(xx), _ptr(rr), xx.shape[0], _ptr(g), 1 if round_bf16 else 0)
+    return float(loss), g
 
 
 def sorted_blocks(keys: np.ndarray, *arrays):

@@ -69,6 +69,15 @@ int64_t orc_export(const orc_volume *v, int32_t *keys, double *T, double *P, int
 /* Allocate (if needed) block (bx, by, bz) and overwrite its 512 voxels. */
 int orc_set_block(orc_volume *v, const int32_t key[3], const double *T, const double *P);
 
+/* Learned noise model (mlp.c): 4-32-32-1 SiLU perceptron predicting
+ * log sigma^2 (m^2) from per-pixel features; bf16 rounding at fixed points. */
+int orc_mlp_param_count(void);
+double orc_bf16(double x);
+void orc_mlp_features(const float *depth, int32_t W, int32_t H, const double K[4], double *feat, int32_t *valid);
+void orc_mlp_forward(const double *params, const double *x, int64_t n, double *s);
+double orc_mlp_loss_grad(const double *params, const double *x, const double *r, int64_t n, double *grad,
+                         int32_t round_bf16);
+
 /* Scalar update rules (normalised units, chi = any |T| > 1). */
 void orc_alg1_step(double *T, double Tk, double w);
 void orc_alg2_step(double *T, double *Wsum, double Tk, double w, double w_max);
