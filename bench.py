@@ -90,6 +90,8 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
         vol.integrate(depths[k], K, poses[k])
         vol.raycast(K, poses[k], vert, nrm)
     torch.cuda.synchronize()
+    group, tune_ms = vol.autotune_raycast(K, poses[max(warmup - 1, 0)])
+    log(f"{spec.name}: raycast group size {group} ({tune_ms * 1e3:.1f} us on the warm-up volume)")
     vol.reset()
     vol.set_timing(True)
     vol.read_timing(reset=True)
@@ -115,7 +117,7 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
         updates=st["total_updates"], new_blocks=st["total_new_blocks"], candidates=st["total_candidates"],
         allocated_blocks=st["allocated_blocks"], status_flags=st["status_flags"],
         prep_ms=tm["prep_ms"], fuse_ms=tm["fuse_ms"], raycast_ms=tm["raycast_ms"],
-        step_ms=e0.elapsed_time(e1) / steps, wall_s=wall, last_frame_hits=hits,
+        step_ms=e0.elapsed_time(e1) / steps, wall_s=wall, last_frame_hits=hits, raycast_group=group,
         voxel_updates_per_s=st["total_updates"] / (integ_ms * 1e-3),
         raycast_mpix_s=pixels / (tm["raycast_ms"] * 1e-3) / 1e6,
     )
@@ -241,6 +243,7 @@ def main():
         "stage_us_per_frame": {"prep": round(res["prep_avg_us"], 2), "fuse": round(res["fuse_avg_us"], 2),
                                "raycast": round(res["raycast_avg_us"], 2)},
         "updates_per_frame": res["updates"] // args.steps,
+        "raycast_group": res["raycast_group"],
         "roofline": roofline_of(res),
     }
     variants = []

@@ -75,6 +75,9 @@ typedef struct {
     int32_t max_width;         /* largest frame the volume will see */
     int32_t max_height;
     uint32_t max_candidates;   /* candidate blocks per frame; 0 = capacity_blocks */
+    int32_t dense_index;       /* 1: also keep a dense per-block index (4 bytes per virtual block,
+                                  the offset buffer of Section 4) for single-load lookups in the
+                                  raycast; 0: look blocks up through the hash only */
 } tsdf_volume_desc;
 
 typedef struct {
@@ -150,6 +153,19 @@ tsdf_status tsdf_integrate_frame(tsdf_volume *vol, const float *depth_dev, const
  * along the world axes. */
 tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
                          float *vertex_dev, float *normal_dev, hipStream_t stream);
+
+/* Lanes that march one ray together in the raycast (1, 2, 4, 8 or 16; default 8).
+ * Every group size gives the same result; only the speed differs. */
+tsdf_status tsdf_set_raycast_group(tsdf_volume *vol, int32_t group);
+int32_t tsdf_get_raycast_group(const tsdf_volume *vol);
+
+/* Autotuner: raycasts the current volume from pose_c2w with every group size
+ * (`reps` timed launches each after one warm-up, HIP events on `stream`),
+ * keeps the fastest for later raycasts and reports it with its mean time in
+ * milliseconds.  Synchronises `stream`.  The outputs hold the last raycast. */
+tsdf_status tsdf_autotune_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
+                                  float *vertex_dev, float *normal_dev, int32_t reps, hipStream_t stream,
+                                  int32_t *best_group, float *best_ms);
 
 /* Counters and sticky flags; synchronises the stream the volume last used. */
 tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out);

@@ -12,6 +12,7 @@ arrays.  ``mlp.py`` holds the oracle of the learned noise model.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional, Sequence
@@ -237,6 +238,19 @@ def mlp_loss_grad(params, x, r, round_bf16: bool = True):
     g = np.zeros(MLP_PARAMS)
     loss = lib().orc_mlp_loss_grad(_ptr(p), _ptr(xx), _ptr(rr), xx.shape[0], _ptr(g), 1 if round_bf16 else 0)
     return float(loss), g
+
+
+def mlp_variance(depth, K, params, delta: float, coeff: float = 0.0015) -> np.ndarray:
+    """Per-pixel p_hat (delta^2 units) of the learned model: exp(s)/delta^2
+    clamped to [p_q e^-4, p_q e^4] around the quadratic p_q, which also stands
+    in where the features are undefined.  Flattened [H*W]."""
+    d = np.asarray(depth, np.float32)
+    feat, valid = mlp_features(d, K)
+    s = mlp_forward(params, feat)
+    D = d.reshape(-1).astype(np.float64)
+    pq = (coeff * D * D / delta) ** 2
+    pl = np.exp(s) / (delta * delta)
+    return np.where(valid & (D > 0), np.clip(pl, pq * math.exp(-4.0), pq * math.exp(4.0)), pq)
 
 
 def sorted_blocks(keys: np.ndarray, *arrays):

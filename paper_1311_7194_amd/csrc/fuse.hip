@@ -17,7 +17,11 @@
 // updates, since such voxels get chi and are not touched.  The paper reads
 // the sampled block list back to the CPU for allocation; here allocation
 // stays on the device (atomic pool counter, lock-free hash).
+#include <type_traits>
+
 #include "tsdf_internal.h"
+#include "mlp_device.h"
+#include "mlp_features.h"
 
 namespace tsdf {
 
@@ -96,27 +100,62 @@ __device__ inline float measurement_variance(const NoiseParams &noise, float D, 
     return r * r;
 }
 
+struct PrepCandLds {
+    uint32_t set[kLdsSet];
+    uint32_t list[kLdsList];
+};
+// MLP mode: the feature tile and the network scratch are dead before the
+// candidate pass starts, so the three share one region.
+struct PrepMlpLds {
+    union {
+        PrepCandLds cand;
+        FeatLds feat;
+        MlpWaveLds wave[4];
+    } u;
+    MlpParamsLds P;
+};
+
+template <bool kMlp>
 __global__ __launch_bounds__(256) void prep_kernel(VolumeView v, const float *__restrict__ depth, Camera cam,
                                                    NoiseParams noise)
 {
-    __shared__ uint32_t set[kLdsSet];
-    __shared__ uint32_t list[kLdsList];
+    using Lds = typename std::conditional<kMlp, PrepMlpLds, PrepCandLds>::type;
+    __shared__ Lds lds;
     __shared__ uint32_t n_list;
     const int tid = threadIdx.x;
-    for (int k = tid; k < kLdsSet; k += 256) set[k] = kEmptyKey;
-    if (tid == 0) n_list = 0;
-    __syncthreads();
-
     const int i = blockIdx.x * kTile + (tid & (kTile - 1));
     const int j = blockIdx.y * kTile + (tid / kTile);
     const bool in_image = i < cam.width && j < cam.height;
     float D = in_image ? depth[(size_t)j * cam.width + i] : 0.0f;
     const bool valid = in_image && D > 0.0f && isfinite(D);
     const float inv_delta_f = (float)v.inv_delta;
-    if (in_image) {
-        float ph = valid ? measurement_variance(noise, D, inv_delta_f) : 0.0f;
-        v.pixmap[(size_t)j * cam.width + i] = make_float2(valid ? D : 0.0f, ph);
+    float ph = valid ? measurement_variance(noise, D, inv_delta_f) : 0.0f;
+    PrepCandLds *cand;
+    if constexpr (kMlp) {
+        // learned variance: features of this tile, then the network (matrix cores)
+        PrepMlpLds &L = lds;
+        mlp_stage_params(L.P, (const uint16_t *)noise.mlp, tid, 256);
+        float f[4];
+        const bool fok = tile_features(L.u.feat, depth, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
+                                       blockIdx.x * kTile, blockIdx.y * kTile, tid, f);
+        __syncthreads();
+        const float s = mlp_forward_wave(L.P, (const uint16_t *)noise.mlp + MLP_W2, L.u.wave[tid >> 6], f, tid & 63,
+                                         nullptr);
+        if (valid && fok) {
+            const float pl = __expf(s) * inv_delta_f * inv_delta_f;
+            ph = fminf(fmaxf(pl, ph * 0.018315639f), ph * 54.59815f);   // [p_q e^-4, p_q e^4]
+        }
+        __syncthreads();
+        cand = &L.u.cand;
+    } else {
+        cand = &lds;
     }
+    uint32_t *set = cand->set;
+    uint32_t *list = cand->list;
+    for (int k = tid; k < kLdsSet; k += 256) set[k] = kEmptyKey;
+    if (tid == 0) n_list = 0;
+    if (in_image) v.pixmap[(size_t)j * cam.width + i] = make_float2(valid ? D : 0.0f, ph);
+    __syncthreads();
 
     if (valid) {
         // The frustum cell (pixel square x [D - delta, D + delta]) is cut into
@@ -190,7 +229,10 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
                        hipStream_t s)
 {
     dim3 grid((cam.width + kTile - 1) / kTile, (cam.height + kTile - 1) / kTile);
-    hipLaunchKernelGGL(prep_kernel, grid, dim3(256), 0, s, v, depth, cam, noise);
+    if (noise.kind == TSDF_NOISE_MLP)
+        hipLaunchKernelGGL(prep_kernel<true>, grid, dim3(256), 0, s, v, depth, cam, noise);
+    else
+        hipLaunchKernelGGL(prep_kernel<false>, grid, dim3(256), 0, s, v, depth, cam, noise);
     return hipGetLastError();
 }
 
@@ -201,43 +243,41 @@ struct CamF {
     float fx, fy, cx, cy;
 };
 
-// Projective measurement of one voxel (Section 7.1).  x_c, y_c, z_c and
-// s = D - z_c are the defined double-precision values bit for bit (same
-// operations, same order, no contraction).  The nearest-pixel index is first
-// found in float; when the float value lies within its proven error bound
-// of a rounding boundary the defined double expression decides instead, so
-// the index always equals the defined one.
-__device__ __forceinline__ bool measure_voxel(const VolumeView &v, const Camera &cam, const CamF &cf, double xc,
-                                              double yc, double zc, const float2 *__restrict__ pixmap, float &Tk,
-                                              float &pk)
+// Nearest-pixel index of a voxel from its camera coordinates (Section 7.1,
+// projective measurement).  The index is first found in float; the result
+// is returned only when the float value lies farther from a rounding
+// boundary than its proven error bound, so it equals the index of the
+// defined double expression.  Returns the linear pixel index, -1 when the
+// voxel falls outside the image, -2 when the double expression must decide.
+__device__ __forceinline__ int pixel_filter(const Camera &cam, const CamF &cf, double xc, double yc, double zc)
 {
 #pragma clang fp contract(off)
-    if (!(zc > 0.0)) return false;
+    if (!(zc > 0.0)) return -1;
     const float xf = (float)xc, yf = (float)yc, zf = (float)zc;
     const float rz = __builtin_amdgcn_rcpf(zf);
     const float au = cf.fx * xf * rz, av = cf.fy * yf * rz;
     const float uf = au + cf.cx, vf = av + cf.cy;
-    float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
-    // |u_float - u_exact| <= 8.3e-7 |fx x/z| + 6e-8 (|cx| + |u|); 2e-6 doubles it
+    const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
+    // |u_float - u_exact| <= 4.2e-7 |fx x/z| + 6e-8 |cx| + 1.2e-7 |u|; the margin is 4x that
     const float eu = 2e-6f * (fabsf(au) + fabsf(cf.cx) + fabsf(uf)) + 1e-6f;
     const float ev = 2e-6f * (fabsf(av) + fabsf(cf.cy) + fabsf(vf)) + 1e-6f;
     const float du = uf + 0.5f - fu, dv = vf + 0.5f - fv;
-    if (!(du > eu && du < 1.0f - eu && dv > ev && dv < 1.0f - ev)) {
-        const double u = cam.fx * xc / zc + cam.cx;
-        const double w = cam.fy * yc / zc + cam.cy;
-        const double fu64 = floor(u + 0.5), fw64 = floor(w + 0.5);
-        if (!(fu64 >= 0.0 && fu64 < (double)cam.width && fw64 >= 0.0 && fw64 < (double)cam.height)) return false;
-        fu = (float)fu64;
-        fv = (float)fw64;
-    }
-    if (!(fu >= 0.0f && fu < (float)cam.width && fv >= 0.0f && fv < (float)cam.height)) return false;
-    const float2 pm = pixmap[(size_t)(int)fv * cam.width + (int)fu];
-    if (!(pm.x > 0.0f)) return false;
-    const double s = (double)pm.x - zc;
-    if (!(fabs(s) <= v.delta)) return false;
-    Tk = (float)(s * v.inv_delta);
-    pk = pm.y;
-    return true;
+    if (!(du > eu && du < 1.0f - eu && dv > ev && dv < 1.0f - ev)) return -2;
+    if (!(fu >= 0.0f && fu < (float)cam.width && fv >= 0.0f && fv < (float)cam.height)) return -1;
+    return (int)fv * cam.width + (int)fu;
+}
+
+// The defined double expression: i = floor(fx x_c / z_c + cx + 1/2), same for j.
+// Scalars by value: a reference would force the kernel's camera into scratch.
+__device__ __forceinline__ int pixel_exact(double fx, double fy, double cx, double cy, int width, int height,
+                                        double xc, double yc, double zc)
+{
+#pragma clang fp contract(off)
+    const double u = fx * xc / zc + cx;
+    const double w = fy * yc / zc + cy;
+    const double fu = floor(u + 0.5), fw = floor(w + 0.5);
+    if (!(fu >= 0.0 && fu < (double)width && fw >= 0.0 && fw < (double)height)) return -1;
+    return (int)fw * width + (int)fu;
 }
 
 __device__ __forceinline__ void kalman(float &T, float &P, float Tk, float pk, float q)
@@ -267,6 +307,14 @@ template <>
 __device__ __forceinline__ void store_s<float>(float *p, float x) { *p = x; }
 template <>
 __device__ __forceinline__ void store_s<__half>(__half *p, float x) { *p = __float2half_rn(x); }
+
+// A value as it reads back from storage of type S.
+template <typename S>
+__device__ __forceinline__ float stored_value(float x);
+template <>
+__device__ __forceinline__ float stored_value<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ float stored_value<__half>(float x) { return __half2float(__float2half_rn(x)); }
 
 template <typename S>
 __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
@@ -303,19 +351,54 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
         float Tk[8], pk[8];
         uint32_t vmask = 0;
 #pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            double xc, yc, zc;
-            {
+        for (int half = 0; half < 2; ++half) {
+            // phase 1: camera coordinates (exact doubles) and the float pixel filter
+            double zcs[4];
+            int pix[4];
+            int need_exact = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int z = 4 * half + k;
+                double xc, yc, zc;
+                {
 #pragma clang fp contract(off)
-                const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
-                const double dz = pz - cam.t[2];
-                xc = ax + cam.R[6] * dz;
-                yc = ay + cam.R[7] * dz;
-                zc = az + cam.R[8] * dz;
+                    const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
+                    const double dz = pz - cam.t[2];
+                    xc = ax + cam.R[6] * dz;
+                    yc = ay + cam.R[7] * dz;
+                    zc = az + cam.R[8] * dz;
+                }
+                zcs[k] = zc;
+                pix[k] = pixel_filter(cam, cf, xc, yc, zc);
+                need_exact |= (pix[k] == -2) << k;
             }
-            Tk[z] = kChi;
-            pk[z] = 0.0f;
-            if (measure_voxel(v, cam, cf, xc, yc, zc, pixmap, Tk[z], pk[z])) vmask |= 1u << z;
+            // phase 2 (rare): voxels near a pixel boundary take the double expression
+            if (need_exact) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if ((need_exact >> k) & 1) {
+#pragma clang fp contract(off)
+                        const double pz = v.origin[2] + ((double)(bz * 8 + 4 * half + k) + 0.5) * v.vs;
+                        const double dz = pz - cam.t[2];
+                        pix[k] = pixel_exact(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
+                                             ax + cam.R[6] * dz, ay + cam.R[7] * dz, zcs[k]);
+                    }
+                }
+            }
+            // phase 3: the gathers, issued together (index 0 stands in for misses)
+            float2 pm[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pm[k] = pixmap[pix[k] >= 0 ? pix[k] : 0];
+            // phase 4: s = D - z_c in double, |s| <= delta
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int z = 4 * half + k;
+                const double sd = (double)pm[k].x - zcs[k];
+                const bool ok = pix[k] >= 0 && pm[k].x > 0.0f && fabs(sd) <= v.delta;
+                Tk[z] = (float)(sd * v.inv_delta);
+                pk[z] = pm[k].y;
+                vmask |= (uint32_t)ok << z;
+            }
         }
         if (lane == 0) {
             uint64_t b = block_linear(v, bx, by, bz);
@@ -343,24 +426,48 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
 
         S *bt = poolT + (size_t)slot * kBlockVoxels + lane;
         S *bp = poolP + (size_t)slot * kBlockVoxels + lane;
+        // lower bound of the block's non-chi values as stored, kept for the raycast
+        uint32_t kmin = kKeyPosInf;
         if (fresh) {
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
                 const bool m = (vmask >> z) & 1u;
                 store_s(bt + 64 * z, m ? Tk[z] : kChi);
                 store_s(bp + 64 * z, m ? pk[z] : 0.0f);
+                if (m) kmin = min(kmin, order_key(stored_value<S>(Tk[z])));
             }
         } else {
+            // phase 5: load every z-slice that holds an update (whole slices:
+            // 64 contiguous voxels), then update and store the valid voxels
+            uint32_t slices = 0;
+#pragma unroll
+            for (int z = 0; z < 8; ++z) slices |= (__ballot((vmask >> z) & 1u) != 0ull) << z;
+            float T[8], P[8];
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                if ((slices >> z) & 1u) {
+                    T[z] = load_s(bt + 64 * z);
+                    P[z] = load_s(bp + 64 * z);
+                }
+            }
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
                 if ((vmask >> z) & 1u) {
-                    float T = load_s(bt + 64 * z);
-                    float P = load_s(bp + 64 * z);
-                    kalman(T, P, Tk[z], pk[z], v.q_hat);
-                    store_s(bt + 64 * z, T);
-                    store_s(bp + 64 * z, P);
+                    kalman(T[z], P[z], Tk[z], pk[z], v.q_hat);
+                    store_s(bt + 64 * z, T[z]);
+                    store_s(bp + 64 * z, P[z]);
+                    if (fabsf(T[z]) <= 1.0f) kmin = min(kmin, order_key(stored_value<S>(T[z])));
                 }
             }
+        }
+        // the owner wavefront folds its new values into the bound (values only
+        // ever lower it, so it stays below the true minimum)
+        kmin = wave_min_u32(kmin);
+        if (lane == 0) {
+            const uint32_t m = fresh ? kmin : min(v.block_min[slot], kmin);
+            v.block_min[slot] = m;
+            if (v.block_index)
+                v.block_index[block_linear(v, bx, by, bz)] = slot | (m > kKeyZero ? kIndexPositive : 0);
         }
         const uint32_t cnt = __popc(vmask);
         acc_upd += cnt;

@@ -1,0 +1,105 @@
+// Per-pixel features of the learned noise model, computed per 16x16 pixel
+// tile with a 16-pixel halo staged in LDS.
+//
+//   f0 = D (metres)
+//   f1 = |cos| between the view ray and the surface normal; the normal is the
+//        cross product of the central differences of the back-projected
+//        neighbours along i and j (all four neighbours valid, pixel not on the
+//        image border); computed in double
+//   f2 = min(Euclidean distance to the nearest depth discontinuity, 16) / 16;
+//        a discontinuity is a valid pixel with an in-image 4-neighbour that is
+//        invalid or differs by more than 5 % of its depth.  Exact separable
+//        transform inside the 33x33 window: min over dy of dy^2 + g(dy)^2,
+//        g = nearest discontinuity along the row
+//   f3 = radial pixel distance to the principal point / fx
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace tsdf {
+
+constexpr int kFeatTile = 16;
+constexpr int kFeatHalo = 16;
+constexpr int kFeatRegion = kFeatTile + 2 * kFeatHalo;   // 48 (discontinuity region)
+constexpr int kFeatDepth = kFeatRegion + 2;              // 50 (depth incl. the neighbour ring)
+
+struct FeatLds {
+    float dep[kFeatDepth][kFeatDepth + 1];   // NaN = outside the image, 0 = no measurement
+    uint8_t disc[kFeatRegion][kFeatRegion];
+    uint8_t g[kFeatRegion][kFeatTile];       // row distance to the nearest discontinuity (17 = none)
+};
+
+// All 256 threads of the workgroup call this (workgroup barriers inside).
+// Thread t handles pixel (i0 + t % 16, j0 + t / 16).  Returns validity.
+__device__ inline bool tile_features(FeatLds &L, const float *__restrict__ depth, int W, int H, double fx, double fy,
+                                     double cx, double cy, int i0, int j0, int tid, float f[4])
+{
+    const float kOut = __uint_as_float(0x7fc00000u);   // quiet NaN: outside the image
+    for (int k = tid; k < kFeatDepth * kFeatDepth; k += 256) {
+        const int r = k / kFeatDepth, c = k % kFeatDepth;
+        const int jj = j0 - kFeatHalo - 1 + r, ii = i0 - kFeatHalo - 1 + c;
+        float d = kOut;
+        if (ii >= 0 && jj >= 0 && ii < W && jj < H) {
+            d = depth[(size_t)jj * W + ii];
+            if (!(d > 0.0f) || !isfinite(d)) d = 0.0f;
+        }
+        L.dep[r][c] = d;
+    }
+    __syncthreads();
+    for (int k = tid; k < kFeatRegion * kFeatRegion; k += 256) {
+        const int r = k / kFeatRegion, c = k % kFeatRegion;
+        const float D = L.dep[r + 1][c + 1];
+        uint8_t dsc = 0;
+        if (D > 0.0f) {   // false for NaN and 0
+            const float nb[4] = {L.dep[r + 1][c + 2], L.dep[r + 1][c], L.dep[r + 2][c + 1], L.dep[r][c + 1]};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (isnan(nb[q])) continue;   // outside the image: does not count
+                if (!(nb[q] > 0.0f) || fabs((double)nb[q] - (double)D) > 0.05 * (double)D) dsc = 1;
+            }
+        }
+        L.disc[r][c] = dsc;
+    }
+    __syncthreads();
+    for (int k = tid; k < kFeatRegion * kFeatTile; k += 256) {
+        const int r = k / kFeatTile, c = k % kFeatTile;
+        int best = 17;
+        for (int dx = -kFeatHalo; dx <= kFeatHalo; ++dx)
+            if (L.disc[r][c + kFeatHalo + dx]) best = min(best, abs(dx));
+        L.g[r][c] = (uint8_t)best;
+    }
+    __syncthreads();
+    const int ti = tid % kFeatTile, tj = tid / kFeatTile;
+    const int i = i0 + ti, j = j0 + tj;
+    const float D = L.dep[tj + kFeatHalo + 1][ti + kFeatHalo + 1];
+    f[0] = f[1] = f[2] = f[3] = 0.0f;
+    if (!(D > 0.0f)) return false;
+    int d2 = 1 << 30;
+    for (int dy = -kFeatHalo; dy <= kFeatHalo; ++dy) {
+        const int gx = L.g[tj + kFeatHalo + dy][ti];
+        d2 = min(d2, dy * dy + gx * gx);
+    }
+    f[0] = D;
+    f[2] = fminf(sqrtf((float)d2), 16.0f) / 16.0f;
+    f[3] = (float)(sqrt((i - cx) * (i - cx) + (j - cy) * (j - cy)) / fx);
+    if (i < 1 || j < 1 || i >= W - 1 || j >= H - 1) return false;
+    const float Dl = L.dep[tj + kFeatHalo + 1][ti + kFeatHalo], Dr = L.dep[tj + kFeatHalo + 1][ti + kFeatHalo + 2];
+    const float Du = L.dep[tj + kFeatHalo][ti + kFeatHalo + 1], Dd = L.dep[tj + kFeatHalo + 2][ti + kFeatHalo + 1];
+    if (!(Dl > 0.0f && Dr > 0.0f && Du > 0.0f && Dd > 0.0f)) return false;
+    const double ax = (i + 1 - cx) / fx * Dr - (i - 1 - cx) / fx * Dl;
+    const double ay = (j - cy) / fy * Dr - (j - cy) / fy * Dl;
+    const double az = (double)Dr - (double)Dl;
+    const double bx = (i - cx) / fx * Dd - (i - cx) / fx * Du;
+    const double by = (j + 1 - cy) / fy * Dd - (j - 1 - cy) / fy * Du;
+    const double bz = (double)Dd - (double)Du;
+    const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+    const double nl = sqrt(nx * nx + ny * ny + nz * nz);
+    const double rx = (i - cx) / fx, ry = (j - cy) / fy;
+    const double rl = sqrt(rx * rx + ry * ry + 1.0);
+    if (!(nl > 0.0)) return false;
+    f[1] = (float)(fabs(nx * rx + ny * ry + nz) / (nl * rl));
+    return true;
+}
+
+}  // namespace tsdf

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "tsdf.h"
 
@@ -43,8 +44,10 @@ struct VolumeView {
     Counters *ctr;
     unsigned long long *hash;   // hash_slots entries: (slot << 32) | key, ~0 = empty
     uint32_t *pool_keys;        // capacity entries: key of the block in each pool slot
+    uint32_t *block_min;        // capacity entries: ordered key of a lower bound of the block's non-chi T
     uint32_t *tile_range;       // raycast: per 8x8 pixel tile (min depth bits, max depth bits)
     uint32_t *occupancy;        // one bit per block of the virtual grid
+    int32_t *block_index;       // optional dense index per virtual block: slot | positive << 30, -1 = empty
     uint32_t *cand_bits;        // per-frame candidate dedup bits (all clear between frames)
     uint32_t *cand_list;        // max_candidates keys
     float2 *pixmap;             // per pixel (depth or 0, measurement variance p_hat)
@@ -138,6 +141,34 @@ __device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
     return -1;
 }
 
+constexpr int32_t kIndexPositive = 1 << 30;   // dense index: every non-chi value of the block is > 0
+constexpr int32_t kIndexSlotMask = kIndexPositive - 1;
+
+// Order-preserving map float -> uint32 (for integer min over floats).
+__host__ __device__ inline uint32_t order_key(float f)
+{
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline float order_value(uint32_t k)
+{
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+constexpr uint32_t kKeyPosInf = 0xff800000u;   // order_key(+inf)
+constexpr uint32_t kKeyZero = 0x80000000u;     // order_key(+0.0f)
+
+// Wave-wide minimum.
+__device__ inline uint32_t wave_min_u32(uint32_t x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, off));
+    return x;
+}
+
 __device__ inline bool occupied(const VolumeView &v, int bx, int by, int bz)
 {
     uint64_t b = block_linear(v, bx, by, bz);
@@ -151,8 +182,8 @@ hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s);
 hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &cam, const NoiseParams &noise,
                        hipStream_t s);
 hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s);
-hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp, float4 *vertex, float4 *normal,
-                          hipStream_t s);
+hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
+                          float4 *normal, hipStream_t s);
 hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
 hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,
                          hipStream_t s);

@@ -83,9 +83,18 @@ __global__ __launch_bounds__(256) void import_kernel(VolumeView v, const int32_t
     if (slot < 0) return;
     S *dT = (S *)v.poolT + (size_t)slot * kBlockVoxels;
     S *dP = (S *)v.poolP + (size_t)slot * kBlockVoxels;
+    uint32_t kmin = kKeyPosInf;
     for (int k = lane; k < kBlockVoxels; k += 64) {
-        dT[k] = T[(size_t)w * kBlockVoxels + k];
+        const S t = T[(size_t)w * kBlockVoxels + k];
+        dT[k] = t;
         dP[k] = P[(size_t)w * kBlockVoxels + k];
+        const float f = (float)t;
+        if (fabsf(f) <= 1.0f) kmin = min(kmin, order_key(f));
+    }
+    kmin = wave_min_u32(kmin);
+    if (lane == 0) {
+        v.block_min[slot] = kmin;
+        if (v.block_index) v.block_index[block_linear(v, bx, by, bz)] = slot | (kmin > kKeyZero ? kIndexPositive : 0);
     }
 }
 
@@ -106,8 +115,9 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // ------------------------------------------------------------ layout
 
 struct Layout {
-    uint64_t state, ctr, hash, occupancy, cand_bits, cand_list, pixmap, pool_keys, tile_range, poolT, poolP, total;
-    uint64_t bitmap_words, tile_words;
+    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range,
+        poolT, poolP, total;
+    uint64_t bitmap_words, tile_words, nblocks;
 };
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -127,6 +137,7 @@ static bool valid_desc(const tsdf_volume_desc *d)
     if (d->storage != TSDF_F32 && d->storage != TSDF_F16) return false;
     if (!(d->q_hat >= 0) || !isfinite(d->q_hat)) return false;
     if (d->max_width <= 0 || d->max_height <= 0 || d->max_width > 16384 || d->max_height > 16384) return false;
+    if (d->dense_index != 0 && d->dense_index != 1) return false;
     return true;
 }
 
@@ -136,6 +147,7 @@ static Layout layout_of(const tsdf_volume_desc *d)
     uint64_t nblocks = 1;
     for (int a = 0; a < 3; ++a) nblocks *= (uint64_t)(d->dims[a] / kBlock);
     L.bitmap_words = (nblocks + 31) / 32;
+    L.nblocks = nblocks;
     uint32_t maxc = d->max_candidates ? d->max_candidates : d->capacity_blocks;
     uint64_t elem = d->storage == TSDF_F16 ? 2 : 4;
     uint64_t off = 0;
@@ -147,6 +159,8 @@ static Layout layout_of(const tsdf_volume_desc *d)
     off = align256(off + 8ull * d->hash_slots);
     L.occupancy = off;
     off = align256(off + 4ull * L.bitmap_words);
+    L.block_index = off;
+    if (d->dense_index) off = align256(off + 4ull * nblocks);
     L.cand_bits = off;
     off = align256(off + 4ull * L.bitmap_words);
     L.cand_list = off;
@@ -154,6 +168,8 @@ static Layout layout_of(const tsdf_volume_desc *d)
     L.pixmap = off;
     off = align256(off + 8ull * (uint64_t)d->max_width * (uint64_t)d->max_height);
     L.pool_keys = off;
+    off = align256(off + 4ull * d->capacity_blocks);
+    L.block_min = off;
     off = align256(off + 4ull * d->capacity_blocks);
     L.tile_words = (uint64_t)((d->max_width + 7) / 8) * (uint64_t)((d->max_height + 7) / 8);
     L.tile_range = off;
@@ -185,6 +201,7 @@ struct tsdf_volume {
     hipStream_t last_stream;
     uint32_t host_flags;   // sticky flags seen by the last tsdf_query_stats
     uint32_t raycast_stamp;
+    int32_t ray_group;     // lanes per ray in the raycast march (1, 2, 4, 8 or 16)
     bool timing;
     std::vector<EventPair> pending;   // recorded, not yet read
     std::vector<hipEvent_t> spare;    // events ready for reuse
@@ -288,6 +305,8 @@ static tsdf_status clear_volume(tsdf_volume *v, hipStream_t s)
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.tile_range) + L.tile_words, L.tile_words, 0u, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.hash), 2ull * v->desc.hash_slots, 0xffffffffu, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.occupancy), L.bitmap_words, 0u, s);
+    if (e == hipSuccess && v->desc.dense_index)
+        e = fill_u32((uint32_t *)(v->base + L.block_index), L.nblocks, 0xffffffffu, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.cand_bits), L.bitmap_words, 0u, s);
     v->host_flags = 0;
     v->last_stream = s;
@@ -339,12 +358,15 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     w.state = (DeviceState *)(v->base + L.state);
     w.ctr = (Counters *)(v->base + L.ctr);
     w.pool_keys = (uint32_t *)(v->base + L.pool_keys);
+    w.block_min = (uint32_t *)(v->base + L.block_min);
     w.tile_range = (uint32_t *)(v->base + L.tile_range);
     w.max_width = desc->max_width;
     w.max_height = desc->max_height;
     v->raycast_stamp = 0;
+    v->ray_group = 8;
     w.hash = (unsigned long long *)(v->base + L.hash);
     w.occupancy = (uint32_t *)(v->base + L.occupancy);
+    w.block_index = desc->dense_index ? (int32_t *)(v->base + L.block_index) : nullptr;
     w.cand_bits = (uint32_t *)(v->base + L.cand_bits);
     w.cand_list = (uint32_t *)(v->base + L.cand_list);
     w.pixmap = (float2 *)(v->base + L.pixmap);
@@ -424,7 +446,7 @@ tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const doubl
     const VolumeView &w = vol->view;
     const uint32_t stamp = ++vol->raycast_stamp == 0 ? ++vol->raycast_stamp : vol->raycast_stamp;
     return hip_status(timed(vol, STAGE_RAYCAST, stream, [&] {
-        return launch_raycast(w, cam, stamp, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
+        return launch_raycast(w, cam, stamp, vol->ray_group, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
     }));
 }
 
@@ -462,6 +484,55 @@ tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out)
     out->reserved = 0;
     vol->host_flags = st.status;
     return TSDF_OK;
+}
+
+tsdf_status tsdf_set_raycast_group(tsdf_volume *vol, int32_t group)
+{
+    if (!vol || !(group == 1 || group == 2 || group == 4 || group == 8 || group == 16)) return TSDF_EINVAL;
+    vol->ray_group = group;
+    return TSDF_OK;
+}
+
+int32_t tsdf_get_raycast_group(const tsdf_volume *vol) { return vol ? vol->ray_group : 0; }
+
+tsdf_status tsdf_autotune_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
+                                  float *vertex_dev, float *normal_dev, int32_t reps, hipStream_t stream,
+                                  int32_t *best_group, float *best_ms)
+{
+    if (!vol || !valid_intrinsics(K) || !valid_pose(pose_c2w) || !vertex_dev || !normal_dev || reps < 1 ||
+        !best_group || !best_ms)
+        return TSDF_EINVAL;
+    if (K->width > vol->desc.max_width || K->height > vol->desc.max_height) return TSDF_EINVAL;
+    const int candidates[5] = {1, 2, 4, 8, 16};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TSDF_EHIP;
+    const bool was_timing = vol->timing;
+    vol->timing = false;
+    float best = 3.4e38f;
+    int bestg = vol->ray_group;
+    tsdf_status st = TSDF_OK;
+    for (int c = 0; c < 5 && st == TSDF_OK; ++c) {
+        vol->ray_group = candidates[c];
+        st = tsdf_raycast(vol, K, pose_c2w, vertex_dev, normal_dev, stream);   // warm-up
+        if (st != TSDF_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) st = TSDF_EHIP;
+        for (int r = 0; r < reps && st == TSDF_OK; ++r) st = tsdf_raycast(vol, K, pose_c2w, vertex_dev, normal_dev, stream);
+        if (st == TSDF_OK && hipEventRecord(e1, stream) != hipSuccess) st = TSDF_EHIP;
+        float ms = 0.0f;
+        if (st == TSDF_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = TSDF_EHIP;
+        if (st == TSDF_OK && ms / reps < best) {
+            best = ms / reps;
+            bestg = candidates[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    vol->timing = was_timing;
+    vol->ray_group = bestg;
+    *best_group = bestg;
+    *best_ms = best;
+    return st;
 }
 
 tsdf_status tsdf_set_timing(tsdf_volume *vol, int32_t enable)

@@ -27,6 +27,7 @@ EXPORTED = [
     "tsdf_volume_bytes", "tsdf_create_volume", "tsdf_destroy_volume", "tsdf_reset_volume",
     "tsdf_integrate_frame", "tsdf_raycast", "tsdf_query_stats", "tsdf_export_blocks",
     "tsdf_import_blocks", "tsdf_status_string", "tsdf_set_timing", "tsdf_read_timing",
+    "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast",
 ]
 
 
@@ -36,7 +37,7 @@ class VolumeDesc(ctypes.Structure):
                 ("capacity_blocks", ctypes.c_uint32), ("hash_slots", ctypes.c_uint32),
                 ("storage", ctypes.c_int32), ("q_hat", ctypes.c_double),
                 ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
-                ("max_candidates", ctypes.c_uint32)]
+                ("max_candidates", ctypes.c_uint32), ("dense_index", ctypes.c_int32)]
 
 
 class Intrinsics(ctypes.Structure):
@@ -96,6 +97,9 @@ def lib():
         L.tsdf_export_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P, P]
         L.tsdf_import_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P]
         L.tsdf_set_timing.argtypes = [P, ctypes.c_int32]
+        L.tsdf_set_raycast_group.argtypes = [P, ctypes.c_int32]
+        L.tsdf_get_raycast_group.argtypes = [P]
+        L.tsdf_autotune_raycast.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P]
         L.tsdf_read_timing.argtypes = [P, P, ctypes.c_int32]
         L.tsdf_status_string.argtypes = [ctypes.c_int]
         L.tsdf_status_string.restype = ctypes.c_char_p
@@ -139,7 +143,8 @@ class Volume:
     def __init__(self, dims: Sequence[int], voxel_size: float, origin: Sequence[float],
                  trunc_voxels: float = 4.0, capacity_blocks: int = 1 << 16, hash_slots: Optional[int] = None,
                  storage: int = F32, q_hat: float = 1e-4, max_width: int = 640, max_height: int = 480,
-                 max_candidates: int = 0, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+                 max_candidates: int = 0, dense_index: bool = True, device: str = "cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
         if hash_slots is None:
             hash_slots = 1
             while hash_slots < 2 * capacity_blocks:
@@ -147,7 +152,7 @@ class Volume:
         self.desc = VolumeDesc((ctypes.c_int32 * 3)(*[int(d) for d in dims]), float(voxel_size),
                                (ctypes.c_double * 3)(*[float(o) for o in origin]), float(trunc_voxels),
                                int(capacity_blocks), int(hash_slots), int(storage), float(q_hat),
-                               int(max_width), int(max_height), int(max_candidates))
+                               int(max_width), int(max_height), int(max_candidates), 1 if dense_index else 0)
         nbytes = ctypes.c_uint64(0)
         _check(lib().tsdf_volume_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)), "tsdf_volume_bytes")
         self.nbytes = int(nbytes.value)
@@ -213,6 +218,26 @@ class Volume:
         st = Stats()
         _check(lib().tsdf_query_stats(self.handle, ctypes.byref(st)), "tsdf_query_stats")
         return st.as_dict()
+
+    def set_raycast_group(self, group: int):
+        _check(lib().tsdf_set_raycast_group(self.handle, int(group)), "tsdf_set_raycast_group")
+
+    @property
+    def raycast_group(self) -> int:
+        return int(lib().tsdf_get_raycast_group(self.handle))
+
+    def autotune_raycast(self, K, pose, reps: int = 3, stream=None):
+        """Times every raycast group size on this view; keeps the fastest."""
+        intr = make_intrinsics(K)
+        vertex = torch.empty((intr.height, intr.width, 4), dtype=torch.float32, device=self.buffer.device)
+        normal = torch.empty_like(vertex)
+        p = _pose_array(pose)
+        best = ctypes.c_int32(0)
+        ms = ctypes.c_float(0)
+        _check(lib().tsdf_autotune_raycast(self.handle, ctypes.byref(intr), p.ctypes.data_as(ctypes.c_void_p),
+                                           _ptr(vertex), _ptr(normal), int(reps), stream_handle(stream),
+                                           ctypes.byref(best), ctypes.byref(ms)), "tsdf_autotune_raycast")
+        return int(best.value), float(ms.value)
 
     def set_timing(self, enable: bool):
         _check(lib().tsdf_set_timing(self.handle, 1 if enable else 0), "tsdf_set_timing")

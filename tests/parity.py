@@ -80,7 +80,7 @@ def compare_raycast(gv, gn, ov, on, oflags, pose, voxel, pixels=None):
     return stats
 
 
-def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None, max_wh=None):
+def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None, max_wh=None, dense_index=True):
     from paper_1311_7194_amd import Volume
 
     g = spec.grid
@@ -89,7 +89,8 @@ def gpu_volume_for(spec, storage=0, q_hat=1e-4, capacity=None, max_wh=None):
     while hs < 2 * cap:
         hs *= 2
     mw, mh = max_wh or (spec.K.width, spec.K.height)
-    return Volume(g.dims, g.voxel_size, g.origin, g.trunc_voxels, cap, hs, storage, q_hat, mw, mh)
+    return Volume(g.dims, g.voxel_size, g.origin, g.trunc_voxels, cap, hs, storage, q_hat, mw, mh,
+                  dense_index=dense_index)
 
 
 def oracle_volume_for(spec, q_hat=1e-4, capacity=None):

@@ -43,11 +43,11 @@ def test_every_declared_symbol_is_exported(lib):
 def desc(**kw):
     d = dict(dims=(256, 256, 256), voxel_size=0.004, origin=(-0.5, -0.5, 0.2), trunc_voxels=4.0,
              capacity_blocks=1 << 14, hash_slots=1 << 15, storage=0, q_hat=1e-4, max_width=640,
-             max_height=480, max_candidates=0)
+             max_height=480, max_candidates=0, dense_index=1)
     d.update(kw)
     return T.VolumeDesc((ctypes.c_int32 * 3)(*d["dims"]), d["voxel_size"], (ctypes.c_double * 3)(*d["origin"]),
                         d["trunc_voxels"], d["capacity_blocks"], d["hash_slots"], d["storage"], d["q_hat"],
-                        d["max_width"], d["max_height"], d["max_candidates"])
+                        d["max_width"], d["max_height"], d["max_candidates"], d["dense_index"])
 
 
 def nbytes(lib, dd):
@@ -78,6 +78,7 @@ def test_volume_bytes_accounts_for_pool_and_index(lib):
     dict(storage=7),
     dict(q_hat=-1e-3),
     dict(max_width=0),
+    dict(dense_index=2),
 ])
 def test_invalid_descriptions_rejected(lib, bad):
     rc, _ = nbytes(lib, desc(**bad))

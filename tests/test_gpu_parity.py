@@ -80,15 +80,18 @@ def test_constant_variance_zero_q(tsdf):
     compare_volumes(gv, ov)
 
 
-def test_raycast_of_imported_oracle_volume(tsdf):
-    """The oracle's volume copied into the GPU: raycasts must agree."""
+@pytest.mark.parametrize("group,dense", [(8, True), (1, True), (16, True), (4, False), (2, True)])
+def test_raycast_of_imported_oracle_volume(tsdf, group, dense):
+    """The oracle's volume copied into the GPU: raycasts must agree for every
+    ray group size, with the dense index and through the hash alone."""
     spec = small_orbit(width=96, height=72, n_frames=3, G=256, vs=0.008)
     ov = oracle_volume_for(spec)
     for k in range(3):
         d, p = sequence_frame(spec, k)
         ov.integrate(d.numpy(), Kvec(spec.K), p)
     keys, T, P = ov.export()
-    gv = gpu_volume_for(spec, max_wh=(128, 96))
+    gv = gpu_volume_for(spec, max_wh=(128, 96), dense_index=dense)
+    gv.set_raycast_group(group)
     gv.import_blocks(torch.from_numpy(keys), torch.from_numpy(T).float(), torch.from_numpy(P).float())
     K = Intrinsics(110.0, 110.0, 60.3, 40.7, 121, 83)   # another camera, ragged size
     pose = look_at((0.9, 0.6, -0.7), (0.0, 0.1, 0.0))
@@ -96,5 +99,5 @@ def test_raycast_of_imported_oracle_volume(tsdf):
     torch.cuda.synchronize()
     ovv, onn, ofl = ov.raycast(Kvec(K), pose, K.width, K.height, n_threads=8)
     rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, spec.grid.voxel_size)
-    print("[parity] imported raycast", rs, flush=True)
+    print(f"[parity] imported raycast G={group} dense={dense}", rs, flush=True)
     assert rs["hits"] > 1000
