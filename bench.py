@@ -77,17 +77,20 @@ def fuse_bytes(st, elem, pixels):
     return (4 * elem * upd_old + 2 * 512 * elem * st["total_new_blocks"] + 8 * pixels + 4 * st["total_candidates"])
 
 
-def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
+def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=None):
+    """noise: None (quadratic) or bf16 MLP parameters (learned variance).
+    frames: pre-generated (depths, poses) to reuse."""
     from paper_1311_7194_amd import Volume
 
     K = spec.K
     vol = Volume.from_grid(spec.grid, storage=storage, q_hat=q_hat, max_width=K.width, max_height=K.height)
     log(f"{spec.name}: volume {vol.nbytes / 2**30:.2f} GiB, generating {steps} frames")
-    depths, poses = generate(spec, max(steps, warmup))
+    depths, poses = frames if frames is not None else generate(spec, max(steps, warmup))
+    kind = 0 if noise is None else 2
     vert = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(vert)
     for k in range(warmup):
-        vol.integrate(depths[k], K, poses[k])
+        vol.integrate(depths[k], K, poses[k], kind, 0.0015, noise)
         vol.raycast(K, poses[k], vert, nrm)
     torch.cuda.synchronize()
     group, tune_ms = vol.autotune_raycast(K, poses[max(warmup - 1, 0)])
@@ -100,7 +103,7 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
     t0 = time.perf_counter()
     e0.record()
     for k in range(steps):
-        vol.integrate(depths[k], K, poses[k])
+        vol.integrate(depths[k], K, poses[k], kind, 0.0015, noise)
         vol.raycast(K, poses[k], vert, nrm)
     e1.record()
     torch.cuda.synchronize()
@@ -115,6 +118,7 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
         workload=spec.name, storage="f16" if storage == 1 else "f32", frames=steps,
         grid=spec.grid.dims[0], voxel_mm=spec.grid.voxel_size * 1e3, width=K.width, height=K.height,
         updates=st["total_updates"], new_blocks=st["total_new_blocks"], candidates=st["total_candidates"],
+        touched_blocks=st["total_touched_blocks"],
         allocated_blocks=st["allocated_blocks"], status_flags=st["status_flags"],
         prep_ms=tm["prep_ms"], fuse_ms=tm["fuse_ms"], raycast_ms=tm["raycast_ms"],
         step_ms=e0.elapsed_time(e1) / steps, wall_s=wall, last_frame_hits=hits, raycast_group=group,
@@ -130,6 +134,7 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4):
     # raycast algorithmic bytes counted as its output only (32 B per pixel): a lower bound
     res["raycast_gbs_output_only"] = 32 * pixels / (tm["raycast_ms"] * 1e-3) / 1e9
     res["_vol"] = vol
+    res["_frames"] = (depths, poses)
     return res
 
 
@@ -209,6 +214,9 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="also run the 4096^3 hand sequence in FP32 and FP16")
     ap.add_argument("--variant-steps", type=int, default=300)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size reference "
+                         "dispatch for the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -219,6 +227,14 @@ def main():
     import paper_1311_7194_amd as tsdf
 
     tsdf.lib()  # fails loudly when the HIP library is missing
+    if args.copy_mib:
+        n = args.copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"reference copy: {n} bytes read, {n} bytes written")
+        del src, dst
     storage = 1 if args.storage == "f16" else 0
     spec = make_spec(args.config, args.steps)
     res = run_sequence(spec, storage, args.steps, args.warmup)
@@ -247,6 +263,19 @@ def main():
         "roofline": roofline_of(res),
     }
     variants = []
+    if args.variants:
+        # learned variance on the same frames (network cost does not depend on the weights)
+        import paper_1311_7194_amd.mlp as M
+
+        params = M.params_from_values(M.init_params(0))
+        rl = run_sequence(spec, storage, args.steps, args.warmup, noise=params, frames=res["_frames"])
+        variants.append({"workload": rl["workload"], "noise": "learned-mlp", "storage": rl["storage"],
+                         "frames": rl["frames"], "voxel_updates_per_s": round(rl["voxel_updates_per_s"], 1),
+                         "prep_us_per_frame": round(rl["prep_avg_us"], 2),
+                         "vs_plain_prep_us_per_frame": round(res["prep_avg_us"], 2),
+                         "updates_per_frame": rl["updates"] // rl["frames"]})
+        log(json.dumps({k: v for k, v in rl.items() if not k.startswith("_")}))
+        del rl
     if args.variants and args.config != "c3":
         spec3 = make_spec("c3", args.variant_steps)
         r32 = run_sequence(spec3, 0, args.variant_steps, 3)

@@ -108,6 +108,8 @@ typedef struct {
     uint64_t total_candidates;
     uint64_t total_new_blocks;
     uint64_t frames;              /* integrate calls since creation or reset */
+    uint64_t frame_touched_blocks;/* blocks that received an update in the last integrate */
+    uint64_t total_touched_blocks;
     uint32_t status_flags;        /* TSDF_FLAG_* (sticky) */
     uint32_t reserved;
 } tsdf_stats;

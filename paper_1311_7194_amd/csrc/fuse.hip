@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
     S *__restrict__ poolT = (S *)v.poolT;
     S *__restrict__ poolP = (S *)v.poolP;
     const CamF cf{(float)cam.fx, (float)cam.fy, (float)cam.cx, (float)cam.cy};
-    uint32_t acc_upd = 0, acc_fresh = 0, acc_new = 0;
+    uint32_t acc_upd = 0, acc_fresh = 0, acc_new = 0, acc_touched = 0;
 
     for (uint32_t c = wave; c < ncand; c += nwaves) {
         const uint32_t key = v.cand_list[c];
@@ -473,6 +473,7 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
         acc_upd += cnt;
         acc_fresh += fresh ? cnt : 0u;
         acc_new += (uint32_t)fresh;   // same value in every lane after the broadcast
+        acc_touched += 1u;
     }
     // wave totals (acc_new is identical in every lane: count it once)
 #pragma unroll
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
         acc_upd += __shfl_xor(acc_upd, off);
         acc_fresh += __shfl_xor(acc_fresh, off);
     }
-    if (lane == 0 && (acc_upd | acc_new)) {
+    if (lane == 0 && (acc_upd | acc_new | acc_touched)) {
         const int l = wave & (kCtrLanes - 1);
         atomicAdd(&v.ctr->frame[l][CTR_UPDATES], (unsigned long long)acc_upd);
         atomicAdd(&v.ctr->total[l][CTR_UPDATES], (unsigned long long)acc_upd);
@@ -488,6 +489,8 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
         atomicAdd(&v.ctr->total[l][CTR_FRESH], (unsigned long long)acc_fresh);
         atomicAdd(&v.ctr->frame[l][CTR_NEW], (unsigned long long)acc_new);
         atomicAdd(&v.ctr->total[l][CTR_NEW], (unsigned long long)acc_new);
+        atomicAdd(&v.ctr->frame[l][CTR_TOUCHED], (unsigned long long)acc_touched);
+        atomicAdd(&v.ctr->total[l][CTR_TOUCHED], (unsigned long long)acc_touched);
     }
 }
 

@@ -32,7 +32,7 @@ static_assert(sizeof(DeviceState) == 256, "state line");
 // Event counters, spread over kCtrLanes addresses so that thousands of
 // wavefronts do not serialise on one atomic; the host sums the lanes.
 constexpr int kCtrLanes = 256;
-enum { CTR_UPDATES = 0, CTR_FRESH = 1, CTR_NEW = 2, CTR_N = 4 };
+enum { CTR_UPDATES = 0, CTR_FRESH = 1, CTR_NEW = 2, CTR_TOUCHED = 3, CTR_N = 4 };
 struct Counters {
     unsigned long long frame[kCtrLanes][CTR_N];
     unsigned long long total[kCtrLanes][CTR_N];

@@ -480,6 +480,8 @@ tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out)
     out->total_candidates = st.total_candidates;
     out->total_new_blocks = tot[CTR_NEW];
     out->frames = st.frames;
+    out->frame_touched_blocks = fr[CTR_TOUCHED];
+    out->total_touched_blocks = tot[CTR_TOUCHED];
     out->status_flags = st.status;
     out->reserved = 0;
     vol->host_flags = st.status;

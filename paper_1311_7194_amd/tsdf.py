@@ -55,6 +55,7 @@ class Stats(ctypes.Structure):
                 ("frame_fresh_updates", ctypes.c_uint64), ("total_updates", ctypes.c_uint64),
                 ("total_fresh_updates", ctypes.c_uint64), ("total_candidates", ctypes.c_uint64),
                 ("total_new_blocks", ctypes.c_uint64), ("frames", ctypes.c_uint64),
+                ("frame_touched_blocks", ctypes.c_uint64), ("total_touched_blocks", ctypes.c_uint64),
                 ("status_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
