@@ -153,6 +153,94 @@ def roofline_of(res):
                 bytes_per_launch=32 * res["width"] * res["height"], avg_launch_us=round(res["raycast_avg_us"], 2))
 
 
+def run_batch_c5(steps=None, warmup=3, reps_tune=3):
+    """The 16-scene batch: step k fuses and raycasts frame k of every scene
+    that still has one, as one graph-captured batched step, timed against
+    the same frames run scene after scene through the single-volume calls
+    (and against the batched step without the graph)."""
+    from paper_1311_7194_amd import Batch, Volume
+    from synthetic.configs import config_c5
+
+    specs = [config_c5(i) for i in range(16)]
+    n_steps = max(s.n_frames for s in specs)
+    n_steps = n_steps if steps is None else min(steps, n_steps)
+    t0 = time.perf_counter()
+    frames = []
+    for s in specs:
+        frames.append(generate(s, min(s.n_frames, n_steps)))
+    log(f"c5: generated {sum(len(f[0]) for f in frames)} frames in {time.perf_counter() - t0:.1f} s")
+    vols = [Volume.from_grid(s.grid, max_width=s.K.width, max_height=s.K.height) for s in specs]
+    log(f"c5: 16 volumes, {sum(v.nbytes for v in vols) / 2**30:.2f} GiB")
+    batch = Batch(vols, [s.K for s in specs], graph=True)
+    stream = batch.stream
+
+    def step_args(k):
+        d = [f[0][k] if k < len(f[0]) else None for f in frames]
+        p = [f[1][k] if k < len(f[1]) else None for f in frames]
+        return d, p
+
+    def reset_all():
+        for v in vols:
+            v.reset()
+        torch.cuda.synchronize()
+
+    for k in range(min(warmup, n_steps)):
+        batch.step(*step_args(k))
+    torch.cuda.synchronize()
+    last = [f[1][min(warmup, len(f[1])) - 1] for f in frames]
+    group, tune_ms = batch.autotune_raycast(last, reps=reps_tune)
+    log(f"c5: batched raycast group {group} ({tune_ms * 1e3:.1f} us per batched raycast on the warm-up volumes)")
+
+    def timed_batched(graph):
+        reset_all()
+        batch.set_graph(graph)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(n_steps):
+            batch.step(*step_args(k), stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    ms_graph = timed_batched(True)
+    stats_b = [v.stats() for v in vols]
+    ms_nograph = timed_batched(False)
+    # 16 sequential plain runs on the same frames, same raycast group
+    reset_all()
+    for v in vols:
+        v.set_raycast_group(group)
+    vert = [torch.empty((s.K.height, s.K.width, 4), dtype=torch.float32, device="cuda") for s in specs]
+    nrm = [torch.empty_like(x) for x in vert]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i, s in enumerate(specs):
+        d, p = frames[i]
+        for k in range(len(d)):
+            vols[i].integrate(d[k], s.K, p[k])
+            vols[i].raycast(s.K, p[k], vert[i], nrm[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    stats_p = [v.stats() for v in vols]
+    same = all(a[k] == b[k] for a, b in zip(stats_b, stats_p)
+               for k in ("total_updates", "total_new_blocks", "allocated_blocks", "total_candidates"))
+    upd = sum(st["total_updates"] for st in stats_b)
+    pixels = sum(len(f[0]) * s.K.width * s.K.height for f, s in zip(frames, specs))
+    flags = [st["status_flags"] for st in stats_b]
+    fill = max(st["allocated_blocks"] / s.grid.capacity_blocks for st, s in zip(stats_b, specs))
+    res = dict(workload="c5-batch16", scenes=16, steps=n_steps, frames=sum(len(f[0]) for f in frames),
+               updates=upd, pixels=pixels, status_flags=max(flags), max_pool_fill=fill, raycast_group=group,
+               batched_graph_ms=ms_graph, batched_nograph_ms=ms_nograph, sequential_plain_ms=ms_seq,
+               voxel_updates_per_s=upd / (ms_graph * 1e-3),
+               sequential_voxel_updates_per_s=upd / (ms_seq * 1e-3),
+               raycast_pixels_per_s_incl_fusion=pixels / (ms_graph * 1e-3),
+               speedup_vs_sequential=ms_seq / ms_graph, speedup_graph_vs_nograph=ms_nograph / ms_graph,
+               counters_equal_to_sequential=same)
+    del batch, vols
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(spec, frames=2, ray_pixels=2000):
     """The oracle (as it stands) on the host: `frames` frames of integration
     and a seeded sample of raycast pixels of the last frame."""
@@ -213,6 +301,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
     ap.add_argument("--variants", type=int, default=1, help="also run the 4096^3 hand sequence in FP32 and FP16")
     ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=1, help="also run the 16-scene batched workload")
+    ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size reference "
@@ -290,6 +380,10 @@ def main():
             log(json.dumps({k: v for k, v in r.items() if not k.startswith("_")}))
         variants[-1]["vs_f32"] = cmp
         del r32, r16
+    if args.batch:
+        rb = run_batch_c5(args.batch_steps or None)
+        log(json.dumps(rb))
+        variants.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in rb.items()})
     if variants:
         out["variants"] = variants
     if args.cpu_baseline:

@@ -151,13 +151,13 @@ tsdf_status tsdf_integrate_frame(tsdf_volume *vol, const float *depth_dev, const
  * no front-facing zero crossing or the normal is undefined.  The ray through
  * each pixel centre is sampled every half voxel from the camera centre; the
  * first bracket with F > 0 >= F over valid trilinear samples is refined by
- * bisection; the normal is the central difference of F one voxel apart
+ * six quaternary search steps and a final linear interpolation; the normal is the central difference of F one voxel apart
  * along the world axes. */
 tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
                          float *vertex_dev, float *normal_dev, hipStream_t stream);
 
 /* Lanes that march one ray together in the raycast (1, 2, 4, 8 or 16; default 8).
- * Every group size gives the same result; only the speed differs. */
+ * Every group size gives bitwise the same maps; only the speed differs. */
 tsdf_status tsdf_set_raycast_group(tsdf_volume *vol, int32_t group);
 int32_t tsdf_get_raycast_group(const tsdf_volume *vol);
 

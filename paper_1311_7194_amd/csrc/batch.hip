@@ -1,0 +1,444 @@
+// Batched multi-scene step: fusion and raycast of several independent
+// volumes, one frame each, in six launches that cover every scene (frame
+// reset, pixel preparation, persistent block fusion over all scenes'
+// candidates, range reset, persistent range pass over all scenes' blocks,
+// raycast).  The sequence can be captured once into a hipGraph and replayed
+// every step; per-step inputs (depth maps, poses, output maps, which scenes
+// have a frame) live in a device table uploaded before each replay.
+// Every scene runs exactly the kernel bodies of the single-volume path, so
+// its results are identical to fusing and raycasting it alone.
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "fuse_device.h"
+#include "raycast_device.h"
+#include "tsdf_batch.h"
+
+namespace tsdf {
+
+constexpr int kMaxScenes = 64;
+
+struct SceneDesc {
+    VolumeView v;
+    Camera cam;
+    NoiseParams noise;
+    const float *depth;
+    float4 *vertex;
+    float4 *normal;
+    uint32_t active;
+    uint32_t stamp;
+    int32_t tiles_x8, tiles_y8;     // raycast tiles
+    int32_t tiles_x16, tiles_y16;   // preparation tiles
+    uint32_t prep_base;             // first preparation workgroup of this scene
+    uint32_t ray_base;              // first raycast tile of this scene
+};
+
+__device__ __forceinline__ int scene_of(const SceneDesc *__restrict__ sd, int n, uint32_t idx, bool ray)
+{
+    int s = 0;
+    for (int k = 1; k < n; ++k)
+        if ((ray ? sd[k].ray_base : sd[k].prep_base) <= idx) s = k;
+    return s;
+}
+
+__global__ void batch_frame_begin(const SceneDesc *__restrict__ sd)
+{
+    const SceneDesc &d = sd[blockIdx.x];
+    if (d.active) frame_begin_body(d.v.state, d.v.ctr, threadIdx.x);
+}
+
+template <bool kMlp>
+__global__ __launch_bounds__(256) void batch_prep(const SceneDesc *__restrict__ sd, int n)
+{
+    const int s = scene_of(sd, n, blockIdx.x, false);
+    const SceneDesc &d = sd[s];
+    if (!d.active) return;   // the whole workgroup leaves together
+    const uint32_t local = blockIdx.x - d.prep_base;
+    prep_body<kMlp>(d.v, d.depth, d.cam, d.noise, (int)(local % (uint32_t)d.tiles_x16),
+                    (int)(local / (uint32_t)d.tiles_x16));
+}
+
+// Offsets of each scene's share in a concatenation of per-scene counts
+// (candidates or allocated blocks), computed once per workgroup into LDS.
+template <bool kBlocks>
+__device__ __forceinline__ void scene_prefix(const SceneDesc *__restrict__ sd, int n, uint32_t *pre)
+{
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        pre[0] = 0;
+        for (int k = 0; k < n; ++k) {
+            const VolumeView &v = sd[k].v;
+            const uint32_t c = !sd[k].active ? 0u
+                               : kBlocks    ? min(v.state->pool_count, v.capacity)
+                                            : min(v.state->cand_count, v.max_candidates);
+            acc += c;
+            pre[k + 1] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// Scene whose share of the concatenation holds position g (wave-uniform g).
+__device__ __forceinline__ int scene_at(const uint32_t *pre, int n, uint32_t g)
+{
+    int s = 0;
+    for (int k = 1; k < n; ++k) s += pre[k] <= g ? 1 : 0;
+    return __builtin_amdgcn_readfirstlane(s);
+}
+
+// Persistent fusion over the concatenation of every active scene's candidates;
+// a wavefront's counts go to a scene's counters when it moves on to the next.
+template <typename S>
+__global__ __launch_bounds__(256) void batch_fuse(const SceneDesc *__restrict__ sd, int n)
+{
+    __shared__ uint32_t pre[kMaxScenes + 1];
+    scene_prefix<false>(sd, n, pre);
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+    const uint32_t nwaves = gridDim.x * 4u;
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)n && sd[threadIdx.x].active)
+        atomicAdd(&sd[threadIdx.x].v.state->total_candidates,
+                  (unsigned long long)(pre[threadIdx.x + 1] - pre[threadIdx.x]));
+    FuseAcc acc;
+    int cur = -1;
+    for (uint32_t g = wave; g < pre[n]; g += nwaves) {
+        const int s = scene_at(pre, n, g);
+        if (s != cur) {
+            if (cur >= 0) fuse_flush(sd[cur].v, acc, wave, lane);
+            cur = s;
+        }
+        const SceneDesc &d = sd[s];
+        const CamF cf{(float)d.cam.fx, (float)d.cam.fy, (float)d.cam.cx, (float)d.cam.cy};
+        fuse_block<S>(d.v, d.cam, cf, d.v.cand_list[g - pre[s]], lane, acc);
+    }
+    if (cur >= 0) fuse_flush(sd[cur].v, acc, wave, lane);
+}
+
+// One thread per (tile, pixel slot) of every scene's raycast tiles.
+__global__ void batch_range_clear(const SceneDesc *__restrict__ sd, int n, uint32_t total_tiles)
+{
+    const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t tile = (uint32_t)(gt >> 6);
+    if (tile >= total_tiles) return;
+    const SceneDesc &d = sd[scene_of(sd, n, tile, true)];
+    if (!d.active) return;
+    range_clear_body(d.v, d.tiles_x8, d.tiles_y8, d.cam.width, d.cam.height, gt - (long long)d.ray_base * 64);
+}
+
+// Persistent range pass over the concatenation of every active scene's blocks.
+__global__ __launch_bounds__(256) void batch_range(const SceneDesc *__restrict__ sd, int n)
+{
+    __shared__ uint32_t pre[kMaxScenes + 1];
+    scene_prefix<true>(sd, n, pre);
+    for (uint32_t g = blockIdx.x * 256u + threadIdx.x; g < pre[n]; g += gridDim.x * 256u) {
+        int s = 0;
+        for (int k = 1; k < n; ++k) s += pre[k] <= g ? 1 : 0;
+        const SceneDesc &d = sd[s];
+        range_block(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, g - pre[s]);
+    }
+}
+
+// One thread per (tile, ray, lane of the ray's group); wavefronts never
+// straddle tiles (64 G threads per tile), hence never scenes.
+template <typename S, int G, bool kDense>
+__global__ __launch_bounds__(256) void batch_raycast(const SceneDesc *__restrict__ sd, int n, uint32_t total_tiles)
+{
+    const long long gt = (long long)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t tile = (uint32_t)(gt / (64 * G));
+    if (tile >= total_tiles) return;
+    // 64 G consecutive threads share a tile, so the scene is wave-uniform
+    const int s = __builtin_amdgcn_readfirstlane(scene_of(sd, n, tile, true));
+    const SceneDesc &d = sd[s];
+    if (!d.active) return;
+    raycast_body<S, G, kDense>(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, d.vertex, d.normal,
+                               gt - (long long)d.ray_base * 64 * G);
+}
+
+}  // namespace tsdf
+
+using namespace tsdf;
+
+struct tsdf_batch {
+    std::vector<tsdf_volume *> vols;
+    std::vector<tsdf_intrinsics> K;
+    SceneDesc *dev;
+    std::vector<SceneDesc> host;
+    uint32_t prep_total, ray_total;
+    int32_t storage, dense, group;
+    bool use_graph;
+    hipGraphExec_t exec;
+    int32_t graph_key;   // (noise kind, group) the graph was captured for; -1 = none
+};
+
+static bool batch_intrinsics_ok(const tsdf_intrinsics *K)
+{
+    return K && isfinite(K->fx) && isfinite(K->fy) && isfinite(K->cx) && isfinite(K->cy) && K->fx > 0 &&
+           K->fy > 0 && K->width > 0 && K->height > 0 && K->width <= 16384 && K->height <= 16384;
+}
+
+template <typename S, bool kDense>
+static void launch_batch_raycast(int G, dim3 grid, hipStream_t s, const SceneDesc *sd, int n, uint32_t tiles)
+{
+    switch (G) {
+    case 1: hipLaunchKernelGGL((batch_raycast<S, 1, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    case 2: hipLaunchKernelGGL((batch_raycast<S, 2, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    case 4: hipLaunchKernelGGL((batch_raycast<S, 4, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    case 16: hipLaunchKernelGGL((batch_raycast<S, 16, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    default: hipLaunchKernelGGL((batch_raycast<S, 8, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    }
+}
+
+static hipError_t enqueue_raycast(tsdf_batch *b, hipStream_t s)
+{
+    const int n = (int)b->vols.size();
+    hipLaunchKernelGGL(batch_range_clear, dim3((unsigned)(((long long)b->ray_total * 64 + 255) / 256)), dim3(256), 0, s, b->dev, n,
+                       b->ray_total);
+    hipLaunchKernelGGL(batch_range, dim3(2048), dim3(256), 0, s, b->dev, n);
+    const long long threads = (long long)b->ray_total * 64 * b->group;
+    dim3 grid((unsigned)((threads + 255) / 256));
+    if (b->storage == TSDF_F16) {
+        if (b->dense) launch_batch_raycast<__half, true>(b->group, grid, s, b->dev, n, b->ray_total);
+        else launch_batch_raycast<__half, false>(b->group, grid, s, b->dev, n, b->ray_total);
+    } else {
+        if (b->dense) launch_batch_raycast<float, true>(b->group, grid, s, b->dev, n, b->ray_total);
+        else launch_batch_raycast<float, false>(b->group, grid, s, b->dev, n, b->ray_total);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t enqueue_step(tsdf_batch *b, int32_t noise_kind, hipStream_t s)
+{
+    const int n = (int)b->vols.size();
+    hipLaunchKernelGGL(batch_frame_begin, dim3(n), dim3(kCtrLanes), 0, s, b->dev);
+    if (noise_kind == TSDF_NOISE_MLP)
+        hipLaunchKernelGGL(batch_prep<true>, dim3(b->prep_total), dim3(256), 0, s, b->dev, n);
+    else
+        hipLaunchKernelGGL(batch_prep<false>, dim3(b->prep_total), dim3(256), 0, s, b->dev, n);
+    if (b->storage == TSDF_F16)
+        hipLaunchKernelGGL(batch_fuse<__half>, dim3(4096), dim3(256), 0, s, b->dev, n);
+    else
+        hipLaunchKernelGGL(batch_fuse<float>, dim3(4096), dim3(256), 0, s, b->dev, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return enqueue_raycast(b, s);
+}
+
+static bool pose_ok(const double *p)
+{
+    for (int q = 0; q < 12; ++q)
+        if (!isfinite(p[q])) return false;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            const double dot = p[4 * a] * p[4 * c] + p[4 * a + 1] * p[4 * c + 1] + p[4 * a + 2] * p[4 * c + 2];
+            if (fabs(dot - (a == c ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    const double det = p[0] * (p[5] * p[10] - p[6] * p[9]) - p[1] * (p[4] * p[10] - p[6] * p[8]) +
+                       p[2] * (p[4] * p[9] - p[5] * p[8]);
+    return det > 0;
+}
+
+// Validates every scene's arguments, then fills the host table for this step
+// and uploads it (stream-ordered after the previous step's kernels).  With
+// depth_dev null every scene is active and only the raycast reads the table.
+static tsdf_status stage_step(tsdf_batch *b, const float *const *depth_dev, const double *poses,
+                              float *const *vertex_dev, float *const *normal_dev, const tsdf_noise_model *noise,
+                              hipStream_t stream)
+{
+    const int n = (int)b->vols.size();
+    for (int k = 0; k < n; ++k) {
+        if (depth_dev && !depth_dev[k]) continue;
+        if (!vertex_dev[k] || !normal_dev[k] || !pose_ok(poses + 12 * k)) return TSDF_EINVAL;
+    }
+    for (int k = 0; k < n; ++k) {
+        SceneDesc &d = b->host[k];
+        d.active = (!depth_dev || depth_dev[k]) ? 1u : 0u;
+        if (!d.active) continue;
+        tsdf_status st = volume_enqueue(b->vols[k], stream, &d.stamp);
+        if (st != TSDF_OK) return st;
+        const double *p = poses + 12 * k;
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) d.cam.R[3 * r + c] = p[4 * r + c];
+            d.cam.t[r] = p[4 * r + 3];
+        }
+        d.depth = depth_dev ? depth_dev[k] : nullptr;
+        d.vertex = (float4 *)vertex_dev[k];
+        d.normal = (float4 *)normal_dev[k];
+        d.noise.kind = noise ? noise->kind : TSDF_NOISE_QUADRATIC;
+        d.noise.coeff = noise ? (float)noise->coeff : 0.0f;
+        d.noise.mlp = noise ? noise->mlp_params_dev : nullptr;
+    }
+    // pageable source: the copy has read the table when the call returns
+    hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), sizeof(SceneDesc) * n, hipMemcpyHostToDevice, stream);
+    return e == hipSuccess ? TSDF_OK : TSDF_EHIP;
+}
+
+extern "C" {
+
+uint64_t tsdf_batch_bytes(int32_t n_scenes)
+{
+    if (n_scenes <= 0 || n_scenes > kMaxScenes) return 0;
+    return (sizeof(SceneDesc) * (uint64_t)n_scenes + 255) & ~255ull;
+}
+
+tsdf_status tsdf_batch_create(tsdf_volume *const *vols, const tsdf_intrinsics *K, int32_t n, void *dev_buf,
+                              uint64_t bytes, tsdf_batch **out)
+{
+    if (!out) return TSDF_EINVAL;
+    *out = nullptr;
+    if (!vols || !K || n <= 0 || n > kMaxScenes || !dev_buf || bytes < tsdf_batch_bytes(n)) return TSDF_EINVAL;
+    tsdf_batch *b = new (std::nothrow) tsdf_batch;
+    if (!b) return TSDF_ENOMEM;
+    b->dev = (SceneDesc *)dev_buf;
+    b->host.assign(n, SceneDesc());
+    b->prep_total = b->ray_total = 0;
+    b->use_graph = false;
+    b->exec = nullptr;
+    b->graph_key = -1;
+    b->group = 8;
+    for (int k = 0; k < n; ++k) {
+        bool dup = false;
+        for (int q = 0; q < k; ++q) dup |= vols[q] == vols[k];
+        if (!vols[k] || dup || !batch_intrinsics_ok(&K[k])) {
+            delete b;
+            return TSDF_EINVAL;
+        }
+        const VolumeView v = volume_view(vols[k]);
+        if (K[k].width > v.max_width || K[k].height > v.max_height) {
+            delete b;
+            return TSDF_EINVAL;
+        }
+        const int32_t dense = v.block_index != nullptr;
+        if (k == 0) {
+            b->storage = v.storage;
+            b->dense = dense;
+        } else if (v.storage != b->storage || dense != b->dense) {
+            delete b;
+            return TSDF_EINVAL;   // one storage type and index mode per batch
+        }
+        b->vols.push_back(vols[k]);
+        b->K.push_back(K[k]);
+        SceneDesc &d = b->host[k];
+        memset(&d, 0, sizeof(d));
+        d.v = v;
+        d.cam.fx = K[k].fx;
+        d.cam.fy = K[k].fy;
+        d.cam.cx = K[k].cx;
+        d.cam.cy = K[k].cy;
+        d.cam.width = K[k].width;
+        d.cam.height = K[k].height;
+        d.tiles_x16 = (K[k].width + 15) / 16;
+        d.tiles_y16 = (K[k].height + 15) / 16;
+        d.tiles_x8 = (K[k].width + 7) / 8;
+        d.tiles_y8 = (K[k].height + 7) / 8;
+        d.prep_base = b->prep_total;
+        d.ray_base = b->ray_total;
+        b->prep_total += (uint32_t)(d.tiles_x16 * d.tiles_y16);
+        b->ray_total += (uint32_t)(d.tiles_x8 * d.tiles_y8);
+    }
+    *out = b;
+    return TSDF_OK;
+}
+
+void tsdf_batch_destroy(tsdf_batch *b)
+{
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    delete b;
+}
+
+tsdf_status tsdf_batch_set_graph(tsdf_batch *b, int32_t enable)
+{
+    if (!b) return TSDF_EINVAL;
+    b->use_graph = enable != 0;
+    return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_set_raycast_group(tsdf_batch *b, int32_t group)
+{
+    if (!b || !(group == 1 || group == 2 || group == 4 || group == 8 || group == 16)) return TSDF_EINVAL;
+    b->group = group;
+    return TSDF_OK;
+}
+
+int32_t tsdf_batch_get_raycast_group(const tsdf_batch *b) { return b ? b->group : 0; }
+
+tsdf_status tsdf_batch_step(tsdf_batch *b, const float *const *depth_dev, const double *poses_c2w,
+                            float *const *vertex_dev, float *const *normal_dev, const tsdf_noise_model *noise,
+                            hipStream_t stream)
+{
+    if (!b || !depth_dev || !poses_c2w || !vertex_dev || !normal_dev) return TSDF_EINVAL;
+    const int32_t kind = noise ? noise->kind : TSDF_NOISE_QUADRATIC;
+    if (kind != TSDF_NOISE_QUADRATIC && kind != TSDF_NOISE_CONSTANT && kind != TSDF_NOISE_MLP) return TSDF_EINVAL;
+    if (kind == TSDF_NOISE_MLP && !noise->mlp_params_dev) return TSDF_EINVAL;
+    if (noise && (!isfinite(noise->coeff) || noise->coeff < 0)) return TSDF_EINVAL;
+    if (b->use_graph && !stream) return TSDF_EINVAL;   // capture needs a created stream
+    tsdf_status st = stage_step(b, depth_dev, poses_c2w, vertex_dev, normal_dev, noise, stream);
+    if (st != TSDF_OK) return st;
+    if (!b->use_graph) return enqueue_step(b, kind, stream) == hipSuccess ? TSDF_OK : TSDF_EHIP;
+    const int32_t key = kind * 64 + b->group;
+    if (!b->exec || b->graph_key != key) {
+        if (b->exec) {
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TSDF_EHIP;
+        hipError_t e = enqueue_step(b, kind, stream);
+        hipError_t e2 = hipStreamEndCapture(stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return TSDF_EHIP;
+        }
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return TSDF_EHIP;
+        }
+        b->graph_key = key;
+    }
+    return hipGraphLaunch(b->exec, stream) == hipSuccess ? TSDF_OK : TSDF_EHIP;
+}
+
+tsdf_status tsdf_batch_autotune_raycast(tsdf_batch *b, const double *poses_c2w, float *const *vertex_dev,
+                                        float *const *normal_dev, int32_t reps, hipStream_t stream,
+                                        int32_t *best_group, float *best_ms)
+{
+    if (!b || !poses_c2w || !vertex_dev || !normal_dev || reps < 1 || !best_group || !best_ms) return TSDF_EINVAL;
+    tsdf_status st = stage_step(b, nullptr, poses_c2w, vertex_dev, normal_dev, nullptr, stream);
+    if (st != TSDF_OK) return st;
+    const int candidates[5] = {1, 2, 4, 8, 16};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return TSDF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return TSDF_EHIP;
+    }
+    float best = 3.4e38f;
+    int bestg = b->group;
+    for (int c = 0; c < 5 && st == TSDF_OK; ++c) {
+        b->group = candidates[c];
+        if (enqueue_raycast(b, stream) != hipSuccess) st = TSDF_EHIP;
+        if (st == TSDF_OK && hipEventRecord(e0, stream) != hipSuccess) st = TSDF_EHIP;
+        for (int r = 0; r < reps && st == TSDF_OK; ++r)
+            if (enqueue_raycast(b, stream) != hipSuccess) st = TSDF_EHIP;
+        float ms = 0.0f;
+        if (st == TSDF_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = TSDF_EHIP;
+        if (st == TSDF_OK && ms / reps < best) {
+            best = ms / reps;
+            bestg = candidates[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->group = bestg;
+    *best_group = bestg;
+    *best_ms = best;
+    return st;
+}
+
+}  // extern "C"

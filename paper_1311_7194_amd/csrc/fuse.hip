@@ -17,24 +17,11 @@
 // updates, since such voxels get chi and are not touched.  The paper reads
 // the sampled block list back to the CPU for allocation; here allocation
 // stays on the device (atomic pool counter, lock-free hash).
-#include <type_traits>
-
-#include "tsdf_internal.h"
-#include "mlp_device.h"
-#include "mlp_features.h"
+#include "fuse_device.h"
 
 namespace tsdf {
 
-__global__ void frame_begin_kernel(DeviceState *st, Counters *ctr)
-{
-    const int t = threadIdx.x;
-    if (t < kCtrLanes)
-        for (int c = 0; c < CTR_N; ++c) ctr->frame[t][c] = 0;
-    if (t == 0) {
-        st->cand_count = 0;
-        st->frames += 1;
-    }
-}
+__global__ void frame_begin_kernel(DeviceState *st, Counters *ctr) { frame_begin_body(st, ctr, threadIdx.x); }
 
 hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s)
 {
@@ -42,187 +29,11 @@ hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- prep
-
-constexpr int kTile = 16;             // 16x16 pixels per workgroup
-constexpr int kLdsSet = 2048;         // LDS hash set of block keys
-constexpr int kLdsList = 1024;        // unique keys held for the global pass
-constexpr int kSubRanges = 4;         // depth sub-intervals of a pixel's frustum cell
-
-// Marks `key` as a candidate of this frame; the first marker appends it to
-// the candidate list.  Called by the active lanes of one wavefront.
-__device__ inline void global_candidate(const VolumeView &v, uint32_t key)
-{
-    int bx, by, bz;
-    unpack_key(key, bx, by, bz);
-    uint64_t b = block_linear(v, bx, by, bz);
-    uint32_t bit = 1u << (b & 31);
-    uint32_t old = atomicOr(&v.cand_bits[b >> 5], bit);
-    bool fresh = !(old & bit);
-    unsigned long long m = __ballot(fresh);
-    if (!m) return;
-    int lane = __lane_id();
-    int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&v.state->cand_count, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (fresh) {
-        uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (idx < v.max_candidates) {
-            v.cand_list[idx] = key;
-        } else {
-            atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
-            atomicAnd(&v.cand_bits[b >> 5], ~bit);
-        }
-    }
-}
-
-// Single-lane version for keys that did not fit the LDS set.
-__device__ inline void global_candidate_lane(const VolumeView &v, uint32_t key, int bx, int by, int bz)
-{
-    uint64_t b = block_linear(v, bx, by, bz);
-    uint32_t bit = 1u << (b & 31);
-    uint32_t old = atomicOr(&v.cand_bits[b >> 5], bit);
-    if (old & bit) return;
-    uint32_t idx = atomicAdd(&v.state->cand_count, 1u);
-    if (idx < v.max_candidates) {
-        v.cand_list[idx] = key;
-    } else {
-        atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
-        atomicAnd(&v.cand_bits[b >> 5], ~bit);
-    }
-}
-
-__device__ inline float measurement_variance(const NoiseParams &noise, float D, float inv_delta)
-{
-    if (noise.kind == TSDF_NOISE_CONSTANT) return noise.coeff;
-    float r = noise.coeff * D * D * inv_delta;   // sigma / delta
-    return r * r;
-}
-
-struct PrepCandLds {
-    uint32_t set[kLdsSet];
-    uint32_t list[kLdsList];
-};
-// MLP mode: the feature tile and the network scratch are dead before the
-// candidate pass starts, so the three share one region.
-struct PrepMlpLds {
-    union {
-        PrepCandLds cand;
-        FeatLds feat;
-        MlpWaveLds wave[4];
-    } u;
-    MlpParamsLds P;
-};
-
 template <bool kMlp>
 __global__ __launch_bounds__(256) void prep_kernel(VolumeView v, const float *__restrict__ depth, Camera cam,
                                                    NoiseParams noise)
 {
-    using Lds = typename std::conditional<kMlp, PrepMlpLds, PrepCandLds>::type;
-    __shared__ Lds lds;
-    __shared__ uint32_t n_list;
-    const int tid = threadIdx.x;
-    const int i = blockIdx.x * kTile + (tid & (kTile - 1));
-    const int j = blockIdx.y * kTile + (tid / kTile);
-    const bool in_image = i < cam.width && j < cam.height;
-    float D = in_image ? depth[(size_t)j * cam.width + i] : 0.0f;
-    const bool valid = in_image && D > 0.0f && isfinite(D);
-    const float inv_delta_f = (float)v.inv_delta;
-    float ph = valid ? measurement_variance(noise, D, inv_delta_f) : 0.0f;
-    PrepCandLds *cand;
-    if constexpr (kMlp) {
-        // learned variance: features of this tile, then the network (matrix cores)
-        PrepMlpLds &L = lds;
-        mlp_stage_params(L.P, (const uint16_t *)noise.mlp, tid, 256);
-        float f[4];
-        const bool fok = tile_features(L.u.feat, depth, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
-                                       blockIdx.x * kTile, blockIdx.y * kTile, tid, f);
-        __syncthreads();
-        const float s = mlp_forward_wave(L.P, (const uint16_t *)noise.mlp + MLP_W2, L.u.wave[tid >> 6], f, tid & 63,
-                                         nullptr);
-        if (valid && fok) {
-            const float pl = __expf(s) * inv_delta_f * inv_delta_f;
-            ph = fminf(fmaxf(pl, ph * 0.018315639f), ph * 54.59815f);   // [p_q e^-4, p_q e^4]
-        }
-        __syncthreads();
-        cand = &L.u.cand;
-    } else {
-        cand = &lds;
-    }
-    uint32_t *set = cand->set;
-    uint32_t *list = cand->list;
-    for (int k = tid; k < kLdsSet; k += 256) set[k] = kEmptyKey;
-    if (tid == 0) n_list = 0;
-    if (in_image) v.pixmap[(size_t)j * cam.width + i] = make_float2(valid ? D : 0.0f, ph);
-    __syncthreads();
-
-    if (valid) {
-        // The frustum cell (pixel square x [D - delta, D + delta]) is cut into
-        // kSubRanges depth slices; each slice's world box gives candidate
-        // blocks (those whose voxel centres the box may contain).
-        const double z0 = fmax((double)D - v.delta, 0.0), z1 = (double)D + v.delta;
-        const double ul = (i - 0.5 - cam.cx) / cam.fx, uh = (i + 0.5 - cam.cx) / cam.fx;
-        const double vl = (j - 0.5 - cam.cy) / cam.fy, vh = (j + 0.5 - cam.cy) / cam.fy;
-        const double pad = 0.01 * v.vs;
-        for (int sr = 0; sr < kSubRanges; ++sr) {
-            const double za = z0 + (z1 - z0) * sr / kSubRanges;
-            const double zb = (sr == kSubRanges - 1) ? z1 : z0 + (z1 - z0) * (sr + 1) / kSubRanges;
-            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const double z = (k & 4) ? zb : za;
-                const double xc = ((k & 1) ? uh : ul) * z, yc = ((k & 2) ? vh : vl) * z;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const double xw = cam.R[3 * a] * xc + cam.R[3 * a + 1] * yc + cam.R[3 * a + 2] * z + cam.t[a];
-                    lo[a] = fmin(lo[a], xw);
-                    hi[a] = fmax(hi[a], xw);
-                }
-            }
-            int b0[3], b1[3];
-            bool empty = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double g0 = ceil((lo[a] - pad - v.origin[a]) * v.inv_vs - 0.5);
-                double g1 = floor((hi[a] + pad - v.origin[a]) * v.inv_vs - 0.5);
-                g0 = fmax(g0, 0.0);
-                g1 = fmin(g1, (double)(v.dims[a] - 1));
-                empty |= !(g0 <= g1);
-                b0[a] = empty ? 0 : (int)g0 >> 3;
-                b1[a] = empty ? -1 : (int)g1 >> 3;
-            }
-            if (empty) continue;
-            for (int bz = b0[2]; bz <= b1[2]; ++bz)
-                for (int by = b0[1]; by <= b1[1]; ++by)
-                    for (int bx = b0[0]; bx <= b1[0]; ++bx) {
-                        const uint32_t key = pack_key(bx, by, bz);
-                        uint32_t h = hash_key(key) & (kLdsSet - 1);
-                        bool placed = false;
-                        for (int p = 0; p < 64; ++p) {
-                            uint32_t prev = atomicCAS(&set[h], kEmptyKey, key);
-                            if (prev == kEmptyKey) {
-                                uint32_t slot = atomicAdd(&n_list, 1u);
-                                if (slot < (uint32_t)kLdsList) {
-                                    list[slot] = key;
-                                    placed = true;
-                                }
-                                break;
-                            }
-                            if (prev == key) {
-                                placed = true;
-                                break;
-                            }
-                            h = (h + 1) & (kLdsSet - 1);
-                        }
-                        // LDS set or list exhausted: go straight to the frame-wide dedup
-                        if (!placed) global_candidate_lane(v, key, bx, by, bz);
-                    }
-        }
-    }
-    __syncthreads();
-    const uint32_t n = min(n_list, (uint32_t)kLdsList);
-    for (uint32_t k = tid; k < n; k += 256) global_candidate(v, list[k]);
+    prep_body<kMlp>(v, depth, cam, noise, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &cam, const NoiseParams &noise,
@@ -236,86 +47,6 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- fuse
-
-// Camera parameters in float for the pixel-index filter.
-struct CamF {
-    float fx, fy, cx, cy;
-};
-
-// Nearest-pixel index of a voxel from its camera coordinates (Section 7.1,
-// projective measurement).  The index is first found in float; the result
-// is returned only when the float value lies farther from a rounding
-// boundary than its proven error bound, so it equals the index of the
-// defined double expression.  Returns the linear pixel index, -1 when the
-// voxel falls outside the image, -2 when the double expression must decide.
-__device__ __forceinline__ int pixel_filter(const Camera &cam, const CamF &cf, double xc, double yc, double zc)
-{
-#pragma clang fp contract(off)
-    if (!(zc > 0.0)) return -1;
-    const float xf = (float)xc, yf = (float)yc, zf = (float)zc;
-    const float rz = __builtin_amdgcn_rcpf(zf);
-    const float au = cf.fx * xf * rz, av = cf.fy * yf * rz;
-    const float uf = au + cf.cx, vf = av + cf.cy;
-    const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
-    // |u_float - u_exact| <= 4.2e-7 |fx x/z| + 6e-8 |cx| + 1.2e-7 |u|; the margin is 4x that
-    const float eu = 2e-6f * (fabsf(au) + fabsf(cf.cx) + fabsf(uf)) + 1e-6f;
-    const float ev = 2e-6f * (fabsf(av) + fabsf(cf.cy) + fabsf(vf)) + 1e-6f;
-    const float du = uf + 0.5f - fu, dv = vf + 0.5f - fv;
-    if (!(du > eu && du < 1.0f - eu && dv > ev && dv < 1.0f - ev)) return -2;
-    if (!(fu >= 0.0f && fu < (float)cam.width && fv >= 0.0f && fv < (float)cam.height)) return -1;
-    return (int)fv * cam.width + (int)fu;
-}
-
-// The defined double expression: i = floor(fx x_c / z_c + cx + 1/2), same for j.
-// Scalars by value: a reference would force the kernel's camera into scratch.
-__device__ __forceinline__ int pixel_exact(double fx, double fy, double cx, double cy, int width, int height,
-                                        double xc, double yc, double zc)
-{
-#pragma clang fp contract(off)
-    const double u = fx * xc / zc + cx;
-    const double w = fy * yc / zc + cy;
-    const double fu = floor(u + 0.5), fw = floor(w + 0.5);
-    if (!(fu >= 0.0 && fu < (double)width && fw >= 0.0 && fw < (double)height)) return -1;
-    return (int)fw * width + (int)fu;
-}
-
-__device__ __forceinline__ void kalman(float &T, float &P, float Tk, float pk, float q)
-{
-    // Algorithm 3 in normalised units; chi is any |T| > 1
-    if (fabsf(T) > 1.0f) {
-        T = Tk;
-        P = pk;
-    } else {
-        P = P + q;
-        const float K = P / (P + pk);
-        T = T + K * (Tk - T);
-        P = (1.0f - K) * P;
-    }
-    if (fabsf(T) > 1.0f) T = kChi;
-}
-
-template <typename S>
-__device__ __forceinline__ float load_s(const S *p);
-template <>
-__device__ __forceinline__ float load_s<float>(const float *p) { return *p; }
-template <>
-__device__ __forceinline__ float load_s<__half>(const __half *p) { return __half2float(*p); }
-template <typename S>
-__device__ __forceinline__ void store_s(S *p, float x);
-template <>
-__device__ __forceinline__ void store_s<float>(float *p, float x) { *p = x; }
-template <>
-__device__ __forceinline__ void store_s<__half>(__half *p, float x) { *p = __float2half_rn(x); }
-
-// A value as it reads back from storage of type S.
-template <typename S>
-__device__ __forceinline__ float stored_value(float x);
-template <>
-__device__ __forceinline__ float stored_value<float>(float x) { return x; }
-template <>
-__device__ __forceinline__ float stored_value<__half>(float x) { return __half2float(__float2half_rn(x)); }
-
 template <typename S>
 __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
 {
@@ -324,174 +55,10 @@ __global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
     const uint32_t nwaves = gridDim.x * 4u;
     const uint32_t ncand = min(v.state->cand_count, v.max_candidates);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&v.state->total_candidates, (unsigned long long)ncand);
-    const int lx = lane & 7, ly = lane >> 3;
-    const float2 *__restrict__ pixmap = v.pixmap;
-    S *__restrict__ poolT = (S *)v.poolT;
-    S *__restrict__ poolP = (S *)v.poolP;
     const CamF cf{(float)cam.fx, (float)cam.fy, (float)cam.cx, (float)cam.cy};
-    uint32_t acc_upd = 0, acc_fresh = 0, acc_new = 0, acc_touched = 0;
-
-    for (uint32_t c = wave; c < ncand; c += nwaves) {
-        const uint32_t key = v.cand_list[c];
-        int bx, by, bz;
-        unpack_key(key, bx, by, bz);
-        // x_c = R^T (x - t) = (R00 dx + R10 dy) + R20 dz: the bracket is the
-        // lane's (x, y) part, the last term varies with z
-        double ax, ay, az;
-        {
-#pragma clang fp contract(off)
-            const double px = v.origin[0] + ((double)(bx * 8 + lx) + 0.5) * v.vs;
-            const double py = v.origin[1] + ((double)(by * 8 + ly) + 0.5) * v.vs;
-            const double dx = px - cam.t[0];
-            const double dy = py - cam.t[1];
-            ax = cam.R[0] * dx + cam.R[3] * dy;
-            ay = cam.R[1] * dx + cam.R[4] * dy;
-            az = cam.R[2] * dx + cam.R[5] * dy;
-        }
-        float Tk[8], pk[8];
-        uint32_t vmask = 0;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            // phase 1: camera coordinates (exact doubles) and the float pixel filter
-            double zcs[4];
-            int pix[4];
-            int need_exact = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int z = 4 * half + k;
-                double xc, yc, zc;
-                {
-#pragma clang fp contract(off)
-                    const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
-                    const double dz = pz - cam.t[2];
-                    xc = ax + cam.R[6] * dz;
-                    yc = ay + cam.R[7] * dz;
-                    zc = az + cam.R[8] * dz;
-                }
-                zcs[k] = zc;
-                pix[k] = pixel_filter(cam, cf, xc, yc, zc);
-                need_exact |= (pix[k] == -2) << k;
-            }
-            // phase 2 (rare): voxels near a pixel boundary take the double expression
-            if (need_exact) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if ((need_exact >> k) & 1) {
-#pragma clang fp contract(off)
-                        const double pz = v.origin[2] + ((double)(bz * 8 + 4 * half + k) + 0.5) * v.vs;
-                        const double dz = pz - cam.t[2];
-                        pix[k] = pixel_exact(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
-                                             ax + cam.R[6] * dz, ay + cam.R[7] * dz, zcs[k]);
-                    }
-                }
-            }
-            // phase 3: the gathers, issued together (index 0 stands in for misses)
-            float2 pm[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) pm[k] = pixmap[pix[k] >= 0 ? pix[k] : 0];
-            // phase 4: s = D - z_c in double, |s| <= delta
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int z = 4 * half + k;
-                const double sd = (double)pm[k].x - zcs[k];
-                const bool ok = pix[k] >= 0 && pm[k].x > 0.0f && fabs(sd) <= v.delta;
-                Tk[z] = (float)(sd * v.inv_delta);
-                pk[z] = pm[k].y;
-                vmask |= (uint32_t)ok << z;
-            }
-        }
-        if (lane == 0) {
-            uint64_t b = block_linear(v, bx, by, bz);
-            atomicAnd(&v.cand_bits[b >> 5], ~(1u << (b & 31)));
-        }
-        const unsigned long long any = __ballot(vmask != 0);
-        if (!any) continue;
-
-        int32_t slot = -1;
-        int fresh = 0;
-        if (lane == 0) {
-            slot = hash_find(v, key);
-            if (slot < 0) {
-                slot = hash_insert_unique(v, key);
-                if (slot >= 0) {
-                    fresh = 1;
-                    uint64_t b = block_linear(v, bx, by, bz);
-                    atomicOr(&v.occupancy[b >> 5], 1u << (b & 31));
-                }
-            }
-        }
-        slot = __shfl(slot, 0);
-        fresh = __shfl(fresh, 0);
-        if (slot < 0) continue;
-
-        S *bt = poolT + (size_t)slot * kBlockVoxels + lane;
-        S *bp = poolP + (size_t)slot * kBlockVoxels + lane;
-        // lower bound of the block's non-chi values as stored, kept for the raycast
-        uint32_t kmin = kKeyPosInf;
-        if (fresh) {
-#pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                const bool m = (vmask >> z) & 1u;
-                store_s(bt + 64 * z, m ? Tk[z] : kChi);
-                store_s(bp + 64 * z, m ? pk[z] : 0.0f);
-                if (m) kmin = min(kmin, order_key(stored_value<S>(Tk[z])));
-            }
-        } else {
-            // phase 5: load every z-slice that holds an update (whole slices:
-            // 64 contiguous voxels), then update and store the valid voxels
-            uint32_t slices = 0;
-#pragma unroll
-            for (int z = 0; z < 8; ++z) slices |= (__ballot((vmask >> z) & 1u) != 0ull) << z;
-            float T[8], P[8];
-#pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                if ((slices >> z) & 1u) {
-                    T[z] = load_s(bt + 64 * z);
-                    P[z] = load_s(bp + 64 * z);
-                }
-            }
-#pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                if ((vmask >> z) & 1u) {
-                    kalman(T[z], P[z], Tk[z], pk[z], v.q_hat);
-                    store_s(bt + 64 * z, T[z]);
-                    store_s(bp + 64 * z, P[z]);
-                    if (fabsf(T[z]) <= 1.0f) kmin = min(kmin, order_key(stored_value<S>(T[z])));
-                }
-            }
-        }
-        // the owner wavefront folds its new values into the bound (values only
-        // ever lower it, so it stays below the true minimum)
-        kmin = wave_min_u32(kmin);
-        if (lane == 0) {
-            const uint32_t m = fresh ? kmin : min(v.block_min[slot], kmin);
-            v.block_min[slot] = m;
-            if (v.block_index)
-                v.block_index[block_linear(v, bx, by, bz)] = slot | (m > kKeyZero ? kIndexPositive : 0);
-        }
-        const uint32_t cnt = __popc(vmask);
-        acc_upd += cnt;
-        acc_fresh += fresh ? cnt : 0u;
-        acc_new += (uint32_t)fresh;   // same value in every lane after the broadcast
-        acc_touched += 1u;
-    }
-    // wave totals (acc_new is identical in every lane: count it once)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc_upd += __shfl_xor(acc_upd, off);
-        acc_fresh += __shfl_xor(acc_fresh, off);
-    }
-    if (lane == 0 && (acc_upd | acc_new | acc_touched)) {
-        const int l = wave & (kCtrLanes - 1);
-        atomicAdd(&v.ctr->frame[l][CTR_UPDATES], (unsigned long long)acc_upd);
-        atomicAdd(&v.ctr->total[l][CTR_UPDATES], (unsigned long long)acc_upd);
-        atomicAdd(&v.ctr->frame[l][CTR_FRESH], (unsigned long long)acc_fresh);
-        atomicAdd(&v.ctr->total[l][CTR_FRESH], (unsigned long long)acc_fresh);
-        atomicAdd(&v.ctr->frame[l][CTR_NEW], (unsigned long long)acc_new);
-        atomicAdd(&v.ctr->total[l][CTR_NEW], (unsigned long long)acc_new);
-        atomicAdd(&v.ctr->frame[l][CTR_TOUCHED], (unsigned long long)acc_touched);
-        atomicAdd(&v.ctr->total[l][CTR_TOUCHED], (unsigned long long)acc_touched);
-    }
+    FuseAcc acc;
+    for (uint32_t c = wave; c < ncand; c += nwaves) fuse_block<S>(v, cam, cf, v.cand_list[c], lane, acc);
+    fuse_flush(v, acc, wave, lane);
 }
 
 hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s)

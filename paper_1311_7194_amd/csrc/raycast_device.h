@@ -1,0 +1,510 @@
+// Device bodies of the range pass and the raycast march, shared by the
+// single-volume kernels (raycast.hip) and the batched kernels (batch.hip).
+// See raycast.hip for the method.
+#pragma once
+
+#include "tsdf_internal.h"
+
+namespace tsdf {
+
+constexpr int kRT = 8;                      // raycast tile edge in pixels
+constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
+constexpr int kCellFootprint = 64;          // largest footprint (cells) a block widens cell by cell
+
+// ------------------------------------------------------------ range maps
+
+constexpr int kCellsPerTile = kRT / kCell;   // cells along a tile edge
+
+// Clears the depth spans of one frame: thread gt of a launch space of
+// (tiles x 64) clears cell `gt % 64` of tile `gt / 64` (if the tile has that
+// many cells), and the tile itself.
+__device__ __forceinline__ void range_clear_body(const VolumeView &v, int tiles_x, int tiles_y, int width,
+                                                 int height, long long gt)
+{
+    const long long tile = gt >> 6;
+    const int within = (int)(gt & 63);
+    const long long nt = (long long)tiles_x * tiles_y;
+    if (tile >= nt) return;
+    if (within == 0) {
+        v.tile_range[tile] = kInfBits;
+        v.tile_range[nt + tile] = 0u;
+    }
+    if (within >= kCellsPerTile * kCellsPerTile) return;
+    const int cw = (width + kCell - 1) / kCell, ch = (height + kCell - 1) / kCell;
+    const int ci = (int)(tile % tiles_x) * kCellsPerTile + within % kCellsPerTile;
+    const int cj = (int)(tile / tiles_x) * kCellsPerTile + within / kCellsPerTile;
+    if (ci < cw && cj < ch) {
+        const size_t c = (size_t)cj * cw + ci;
+        v.pix_range[c] = kInfBits;
+        v.pix_range[(size_t)cw * ch + c] = 0u;
+    }
+}
+
+// ------------------------------------------------------------ range pass
+
+// One allocated block (pool slot) of the range pass.
+__device__ __forceinline__ void range_block(const VolumeView &v, const Camera &cam, uint32_t stamp, int tiles_x,
+                                            int tiles_y, uint32_t slot)
+{
+    uint32_t *tmin = v.tile_range;
+    uint32_t *tmax = v.tile_range + (size_t)tiles_x * tiles_y;
+    // camera axes in float: x_c = R^T (x - t)
+    const float R[9] = {(float)cam.R[0], (float)cam.R[1], (float)cam.R[2], (float)cam.R[3], (float)cam.R[4],
+                        (float)cam.R[5], (float)cam.R[6], (float)cam.R[7], (float)cam.R[8]};
+    const float fx = (float)cam.fx, fy = (float)cam.fy, cx = (float)cam.cx, cy = (float)cam.cy;
+    const float bw = (float)(8.0 * v.vs);
+    int bx, by, bz;
+    unpack_key(v.pool_keys[slot], bx, by, bz);
+    // stencil-base box of block B: q in [8B, 8B + 8], x = origin + (q + 1/2) voxel;
+    // its min corner relative to the camera centre, in double then float
+    const float ox = (float)(v.origin[0] + (8.0 * bx + 0.5) * v.vs - cam.t[0]);
+    const float oy = (float)(v.origin[1] + (8.0 * by + 0.5) * v.vs - cam.t[1]);
+    const float oz = (float)(v.origin[2] + (8.0 * bz + 0.5) * v.vs - cam.t[2]);
+    float zlo = 3.4e38f, zhi = -3.4e38f, ulo = 3.4e38f, uhi = -3.4e38f, vlo = 3.4e38f, vhi = -3.4e38f;
+    bool behind = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float dx = ox + ((k & 1) ? bw : 0.0f), dy = oy + ((k & 2) ? bw : 0.0f),
+                    dz = oz + ((k & 4) ? bw : 0.0f);
+        const float xc = R[0] * dx + R[3] * dy + R[6] * dz;
+        const float yc = R[1] * dx + R[4] * dy + R[7] * dz;
+        const float zc = R[2] * dx + R[5] * dy + R[8] * dz;
+        zlo = fminf(zlo, zc);
+        zhi = fmaxf(zhi, zc);
+        behind |= !(zc > 1e-4f);
+        const float rz = 1.0f / zc;
+        ulo = fminf(ulo, fx * xc * rz + cx);
+        uhi = fmaxf(uhi, fx * xc * rz + cx);
+        vlo = fminf(vlo, fy * yc * rz + cy);
+        vhi = fmaxf(vhi, fy * yc * rz + cy);
+    }
+    if (zhi <= 0.0f) return;            // wholly behind the camera
+    if (behind) {                         // reaches the camera plane: rays start at the camera
+        v.state->near_stamp = stamp;
+        return;
+    }
+    // pixel centres (i, j) inside the projected box; eps bounds the float
+    // error of the projected corners (positions rounded to float relative to
+    // the camera, then three products and a reciprocal)
+    const float eps = 1e-5f * (fabsf(ulo - cx) + fabsf(uhi - cx) + fabsf(vlo - cy) + fabsf(vhi - cy) + fx + fy) +
+                      1e-3f;
+    const float ulo_e = fmaxf(ulo - eps, -1.0f), uhi_e = fminf(uhi + eps, (float)cam.width);
+    const float vlo_e = fmaxf(vlo - eps, -1.0f), vhi_e = fminf(vhi + eps, (float)cam.height);
+    const int i0 = max((int)ceilf(ulo_e), 0), i1 = min((int)floorf(uhi_e), cam.width - 1);
+    const int j0 = max((int)ceilf(vlo_e), 0), j1 = min((int)floorf(vhi_e), cam.height - 1);
+    if (!(ulo_e <= uhi_e && vlo_e <= vhi_e) || i0 > i1 || j0 > j1) return;
+    const uint32_t zl = __float_as_uint(fmaxf(zlo * (1.0f - 1e-5f) - 1e-6f, 0.0f));
+    const uint32_t zh = __float_as_uint(zhi * (1.0f + 1e-5f) + 1e-6f);
+    const int c0 = i0 / kCell, c1 = i1 / kCell, d0 = j0 / kCell, d1 = j1 / kCell;
+    if ((c1 - c0 + 1) * (d1 - d0 + 1) <= kCellFootprint) {
+        // small footprint: widen the span of every cell it covers
+        const int cw = (cam.width + kCell - 1) / kCell, ch = (cam.height + kCell - 1) / kCell;
+        uint32_t *cmin = v.pix_range, *cmax = v.pix_range + (size_t)cw * ch;
+        for (int d = d0; d <= d1; ++d)
+            for (int c = c0; c <= c1; ++c) {
+                const size_t p = (size_t)d * cw + c;
+                if (cmin[p] > zl) atomicMin(&cmin[p], zl);
+                if (cmax[p] < zh) atomicMax(&cmax[p], zh);
+            }
+        return;
+    }
+    // large footprint (blocks close to the camera): widen whole tiles
+    for (int tj = j0 / kRT; tj <= j1 / kRT; ++tj)
+        for (int ti = i0 / kRT; ti <= i1 / kRT; ++ti) {
+            const size_t t = (size_t)tj * tiles_x + ti;
+            if (tmin[t] > zl) atomicMin(&tmin[t], zl);
+            if (tmax[t] < zh) atomicMax(&tmax[t], zh);
+        }
+}
+
+// ------------------------------------------------------------ march
+
+struct Ray {
+    double q0[3];    // q at s = 0 (camera centre)
+    double dq[3];    // dq/ds
+    double inv[3];   // ds/dq (0 where the ray is parallel to the axis)
+    double d[3];     // unit world direction
+};
+
+template <typename S>
+__device__ __forceinline__ float ld(const S *p);
+template <>
+__device__ __forceinline__ float ld<float>(const float *p) { return *p; }
+template <>
+__device__ __forceinline__ float ld<__half>(const __half *p) { return __half2float(*p); }
+
+// Cached slots of cell block B and its upper neighbours B + {0,1}^3, and
+// whether every non-chi value in those 8 blocks is positive (then no sample
+// of the cell can have F <= 0: F is a convex combination of them).
+struct SlotCache {
+    int B[3];
+    int32_t s[8];
+    bool positive;
+};
+
+// Dense index: one load per neighbour; the entry carries the block's sign flag.
+template <bool kDense>
+__device__ __forceinline__ void fill_cache(const VolumeView &v, SlotCache &c, int bx, int by, int bz)
+{
+    c.B[0] = bx;
+    c.B[1] = by;
+    c.B[2] = bz;
+    bool pos = true;
+    if constexpr (kDense) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int x = bx + (k & 1), y = by + ((k >> 1) & 1), z = bz + ((k >> 2) & 1);
+            const bool in = x < v.nblk[0] && y < v.nblk[1] && z < v.nblk[2];
+            const int32_t e = in ? v.block_index[block_linear(v, x, y, z)] : -1;
+            c.s[k] = e < 0 ? -1 : (e & kIndexSlotMask);
+            pos &= (e < 0) || (e & kIndexPositive);
+        }
+    } else {
+        uint32_t kmin = kKeyPosInf;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int x = bx + (k & 1), y = by + ((k >> 1) & 1), z = bz + ((k >> 2) & 1);
+            int32_t sl = -1;
+            if (x < v.nblk[0] && y < v.nblk[1] && z < v.nblk[2] && occupied(v, x, y, z))
+                sl = hash_find(v, pack_key(x, y, z));
+            c.s[k] = sl;
+            if (sl >= 0) kmin = min(kmin, v.block_min[sl]);
+        }
+        pos = kmin > kKeyZero;
+    }
+    c.positive = pos;
+}
+
+// Trilinear F at integer base c (global voxel indices) with fractions f,
+// using slots from the cache (c must lie in cell c.B).  False when invalid.
+template <typename S>
+__device__ __forceinline__ bool interp_cached(const VolumeView &v, const SlotCache &cache, const int c[3],
+                                              const float f[3], float &F)
+{
+    const S *pool = (const S *)v.poolT;
+    const int l0 = c[0] & 7, l1 = c[1] & 7, l2 = c[2] & 7;
+    float val[8];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+        const int sx = (l0 + ox) >> 3, sy = (l1 + oy) >> 3, sz = (l2 + oz) >> 3;
+        const int sel = sx | (sy << 1) | (sz << 2);
+        int32_t slot = cache.s[0];
+#pragma unroll
+        for (int m = 1; m < 8; ++m) slot = (sel == m) ? cache.s[m] : slot;
+        const int vx = (l0 + ox) & 7, vy = (l1 + oy) & 7, vz = (l2 + oz) & 7;
+        const float T = slot >= 0 ? ld(pool + (size_t)slot * kBlockVoxels + vx + 8 * vy + 64 * vz) : kChi;
+        ok &= fabsf(T) <= 1.0f;
+        val[k] = T;
+    }
+    const float x00 = val[0] + f[0] * (val[1] - val[0]);
+    const float x10 = val[2] + f[0] * (val[3] - val[2]);
+    const float x01 = val[4] + f[0] * (val[5] - val[4]);
+    const float x11 = val[6] + f[0] * (val[7] - val[6]);
+    const float y0 = x00 + f[1] * (x10 - x00);
+    const float y1 = x01 + f[1] * (x11 - x01);
+    F = y0 + f[2] * (y1 - y0);
+    return ok;
+}
+
+__device__ __forceinline__ void q_at(const Ray &r, double s, double q[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = r.q0[a] + s * r.dq[a];
+}
+
+// Stencil base voxel and fractions of q; false outside the grid.
+__device__ __forceinline__ bool stencil(const VolumeView &v, const double q[3], int c[3], float f[3])
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double fl = floor(q[a]);
+        inside &= (fl >= 0.0 && fl + 1.0 <= (double)(v.dims[a] - 1));
+        c[a] = inside ? (int)fl : 0;
+        f[a] = (float)(q[a] - fl);
+    }
+    return inside;
+}
+
+// F at q, refilling the lane's cache when the stencil's base block changes.
+template <typename S, bool kDense>
+__device__ __forceinline__ bool sample_q(const VolumeView &v, SlotCache &cache, const double q[3], float &F)
+{
+    int c[3];
+    float f[3];
+    if (!stencil(v, q, c, f)) return false;
+    if ((c[0] >> 3) != cache.B[0] || (c[1] >> 3) != cache.B[1] || (c[2] >> 3) != cache.B[2])
+        fill_cache<kDense>(v, cache, c[0] >> 3, c[1] >> 3, c[2] >> 3);
+    return interp_cached<S>(v, cache, c, f, F);
+}
+
+// First lattice index past the cell of block B along the ray (the caller's
+// samples before it all have their base voxel in B).
+__device__ __forceinline__ long long cell_exit_sample(const Ray &r, const int B[3], double h)
+{
+    double s_exit = 1e300;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (r.dq[a] > 0.0) s_exit = fmin(s_exit, (8.0 * (B[a] + 1) - r.q0[a]) * r.inv[a]);
+        else if (r.dq[a] < 0.0) s_exit = fmin(s_exit, (8.0 * B[a] - r.q0[a]) * r.inv[a]);
+    }
+    const long long m = (long long)floor(s_exit / h);
+    double qm[3];
+    q_at(r, (double)m * h, qm);
+    const bool still = ((int)floor(qm[0]) >> 3) == B[0] && ((int)floor(qm[1]) >> 3) == B[1] &&
+                       ((int)floor(qm[2]) >> 3) == B[2];
+    return still ? m + 1 : m;
+}
+
+// Shuffle inside a group of G lanes: value of lane `src` of this lane's group.
+template <int G>
+__device__ __forceinline__ int group_lane(int lane, int src) { return (lane & ~(G - 1)) | src; }
+
+// Thread `gt` of a launch space of (tiles x 64 rays x G lanes) for one frame.
+template <typename S, int G, bool kDense>
+__device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &cam, uint32_t stamp, int tiles_x,
+                                             int tiles_y, float4 *__restrict__ vertex, float4 *__restrict__ normal,
+                                             long long gt)
+{
+    static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "group size");
+    const int lane = threadIdx.x & 63;
+    const int j = lane & (G - 1);                       // sample slot inside the ray's group
+    // rays in 8x8-pixel tile order: 64 consecutive rays form one tile
+    const long long ray = gt / G;
+    const long long tile = ray >> 6;
+    const int within = (int)(ray & 63);
+    const int ti = (int)(tile % tiles_x), tj = (int)(tile / tiles_x);
+    const int i = ti * kRT + (within & 7), jpix = tj * kRT + (within >> 3);
+    const bool active = tj < tiles_y && i < cam.width && jpix < cam.height;
+    const double h = 0.5 * v.vs;
+
+    Ray r;
+    long long n_lo = 1, n_end = 0;
+    if (active) {
+        const size_t t = (size_t)tj * tiles_x + ti;
+        // the pixel's cell span joined with its tile's (blocks with large footprints)
+        const int cw = (cam.width + kCell - 1) / kCell, ch = (cam.height + kCell - 1) / kCell;
+        const size_t cell = (size_t)(jpix / kCell) * cw + i / kCell;
+        const float zmin_t = __uint_as_float(min(v.tile_range[t], v.pix_range[cell]));
+        const float zmax_t =
+            __uint_as_float(max(v.tile_range[(size_t)tiles_x * tiles_y + t], v.pix_range[(size_t)cw * ch + cell]));
+        const bool near = v.state->near_stamp == stamp;
+        const double dc0 = (i - cam.cx) / cam.fx, dc1 = (jpix - cam.cy) / cam.fy;
+        const double len = sqrt(dc0 * dc0 + dc1 * dc1 + 1.0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.d[a] = (cam.R[3 * a] * dc0 + cam.R[3 * a + 1] * dc1 + cam.R[3 * a + 2]) / len;
+            r.q0[a] = (cam.t[a] - v.origin[a]) * v.inv_vs - 0.5;
+            r.dq[a] = r.d[a] * v.inv_vs;
+            r.inv[a] = r.dq[a] != 0.0 ? 1.0 / r.dq[a] : 0.0;
+        }
+        // valid samples need every stencil voxel in the grid: q in [0, G-1]
+        double s_in = 0.0, s_out = 1e300;
+        bool miss = !(near || zmin_t <= zmax_t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double hiq = (double)(v.dims[a] - 1);
+            if (r.dq[a] == 0.0) {
+                miss |= (r.q0[a] < 0.0 || r.q0[a] > hiq);
+            } else {
+                const double s0 = (0.0 - r.q0[a]) * r.inv[a], s1 = (hiq - r.q0[a]) * r.inv[a];
+                s_in = fmax(s_in, fmin(s0, s1));
+                s_out = fmin(s_out, fmax(s0, s1));
+            }
+        }
+        if (!near) {   // the depth span (camera z = s / len along this ray)
+            s_in = fmax(s_in, (double)zmin_t * len);
+            s_out = fmin(s_out, (double)zmax_t * len);
+        }
+        if (!miss && s_in <= s_out) {
+            n_lo = max((long long)floor(s_in / h) - 1, 1ll);
+            n_end = (long long)ceil(s_out / h) + 1;
+        }
+    }
+
+    // ---- march: the group evaluates samples n_base .. n_base + G - 1 per step
+    SlotCache cache;
+    cache.B[0] = cache.B[1] = cache.B[2] = -(1 << 30);
+    long long n_base = n_lo;
+    bool done = !(active && n_lo <= n_end);
+    bool hit = false;
+    float Fc = 0.0f;     // carried last sample of the previous step (valid flag vc)
+    bool vc = false;
+    double s_lo = 0.0, s_hi = 0.0;
+    float F_lo = 0.0f, F_hi = 0.0f;
+    while (__ballot(!done)) {
+        const long long n = n_base + j;
+        bool valid = false, cell_empty = false, in_cell = false;
+        float F = 0.0f;
+        if (!done && n <= n_end) {
+            double q[3];
+            q_at(r, (double)n * h, q);
+            int c[3];
+            float f[3];
+            if (stencil(v, q, c, f)) {
+                if ((c[0] >> 3) != cache.B[0] || (c[1] >> 3) != cache.B[1] || (c[2] >> 3) != cache.B[2])
+                    fill_cache<kDense>(v, cache, c[0] >> 3, c[1] >> 3, c[2] >> 3);
+                in_cell = true;   // the cache now describes this sample's cell
+                cell_empty = cache.s[0] < 0;
+                if (!cell_empty) valid = interp_cached<S>(v, cache, c, f, F);
+            }
+        }
+        // pair every sample with its predecessor (lane j - 1, or the carry)
+        const float Fp_sh = __shfl(F, group_lane<G>(lane, (j + G - 1) & (G - 1)));
+        const bool vp_sh = __shfl((int)valid, group_lane<G>(lane, (j + G - 1) & (G - 1))) != 0;
+        const float Fp = j == 0 ? Fc : Fp_sh;
+        const bool vp = j == 0 ? vc : vp_sh;
+        const bool cross = !done && n <= n_end && valid && vp && Fp > 0.0f && F <= 0.0f;
+        const unsigned long long m = __ballot(cross);
+        const uint32_t gm = (uint32_t)(m >> (lane & ~(G - 1))) & ((G == 32 ? 0xffffffffu : (1u << G) - 1u));
+        // (done and gm are the same in every lane of a group, so the group's
+        // lanes all take part in these shuffles)
+        if (!done && gm) {
+            const int first = __builtin_ctz(gm);
+            const long long nh = n_base + first;
+            s_lo = (double)(nh - 1) * h;
+            s_hi = (double)nh * h;
+            F_lo = __shfl(Fp, group_lane<G>(lane, first));
+            F_hi = __shfl(F, group_lane<G>(lane, first));
+            hit = true;
+            done = true;
+        }
+        // advance: the group's last lane decides a jump over its cell
+        const int last = G - 1;
+        const float F_last = __shfl(F, group_lane<G>(lane, last));
+        const bool v_last = __shfl((int)valid, group_lane<G>(lane, last)) != 0;
+        const bool empty_last = __shfl((int)(in_cell && cell_empty), group_lane<G>(lane, last)) != 0;
+        const bool pos_last = __shfl((int)(in_cell && !cell_empty && cache.positive), group_lane<G>(lane, last)) != 0;
+        const int B0 = __shfl(cache.B[0], group_lane<G>(lane, last));
+        const int B1 = __shfl(cache.B[1], group_lane<G>(lane, last));
+        const int B2 = __shfl(cache.B[2], group_lane<G>(lane, last));
+        if (!done) {
+            const long long n_last = n_base + last;
+            long long next = n_last + 1;
+            bool carry = true;
+            if (n_last > n_end) {
+                done = true;
+            } else if (empty_last || pos_last) {
+                const int Bc[3] = {B0, B1, B2};
+                const long long exit_n = cell_exit_sample(r, Bc, h);   // first sample past the cell
+                // empty: every sample before the exit is invalid; positive: none
+                // before the cell's last sample can end a crossing
+                const long long target = empty_last ? exit_n : exit_n - 1;
+                if (target > next) {
+                    next = target;
+                    carry = false;
+                }
+            }
+            Fc = carry ? F_last : 0.0f;
+            vc = carry && v_last;
+            n_base = next;
+            if (n_base > n_end) done = true;
+        }
+    }
+
+    // ---- refinement: quaternary search inside [s_lo, s_hi] (F_lo > 0 >= F_hi).
+    // Each step samples the 3 inner quarter points (point m by lane m % G of
+    // the group, in ceil(3 / G) rounds), so the points and hence the result do
+    // not depend on the group size; 6 steps shrink the bracket 4096-fold.
+    constexpr int kPts = 3, kSteps = 6, kRounds = (kPts + G - 1) / G;
+    double a = s_lo, b = s_hi;
+    float Fa = F_lo, Fb = F_hi;
+    bool refine = hit;
+    for (int it = 0; it < kSteps; ++it) {
+        if (!__ballot(refine)) break;
+        float Fp[kPts];
+        bool vp[kPts];
+#pragma unroll
+        for (int rd = 0; rd < kRounds; ++rd) {
+            const int m = rd * G + j;
+            float Fm = 0.0f;
+            bool vm = false;
+            if (refine && m < kPts) {
+                double qm[3];
+                q_at(r, a + (b - a) * (double)(m + 1) * 0.25, qm);
+                vm = sample_q<S, kDense>(v, cache, qm, Fm);
+            }
+#pragma unroll
+            for (int mm = rd * G; mm < (rd + 1) * G && mm < kPts; ++mm) {
+                Fp[mm] = __shfl(Fm, group_lane<G>(lane, mm - rd * G));
+                vp[mm] = __shfl((int)vm, group_lane<G>(lane, mm - rd * G)) != 0;
+            }
+        }
+        if (refine) {
+            bool bad = false;
+            int k = kPts;   // first non-positive point: the root lies in (point k-1, point k]
+#pragma unroll
+            for (int mm = kPts - 1; mm >= 0; --mm) {
+                bad |= !vp[mm];
+                if (vp[mm] && Fp[mm] <= 0.0f) k = mm;
+            }
+            if (bad) {
+                refine = false;   // an invalid point inside the bracket: keep the bracket
+            } else {
+                float F_km1 = Fa, F_k = Fb;
+#pragma unroll
+                for (int mm = 0; mm < kPts; ++mm) {
+                    if (mm == k - 1) F_km1 = Fp[mm];
+                    if (mm == k) F_k = Fp[mm];
+                }
+                const double na = k == 0 ? a : a + (b - a) * (double)k * 0.25;
+                const double nb = k == kPts ? b : a + (b - a) * (double)(k + 1) * 0.25;
+                Fa = F_km1;
+                Fb = F_k;
+                a = na;
+                b = nb;
+            }
+        }
+    }
+    const double sh = hit ? ((Fa - Fb) > 0.0f ? a + (b - a) * ((double)Fa / ((double)Fa - (double)Fb)) : 0.5 * (a + b))
+                          : 0.0;
+    // ---- normal: central differences one voxel apart, lanes share the 6 samples
+    float g[3] = {0.f, 0.f, 0.f};
+    bool ok = hit;
+    if (__ballot(hit)) {
+        double qh[3];
+        q_at(r, sh, qh);
+        float Fs[6];
+        bool vs[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            Fs[e] = 0.0f;
+            vs[e] = false;
+        }
+        // sample e in {+x, -x, +y, -y, +z, -z} is taken by lane e % G of the group
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            if (hit && (e % G) == j) {
+                double qe[3] = {qh[0], qh[1], qh[2]};
+                qe[e >> 1] += (e & 1) ? -1.0 : 1.0;
+                vs[e] = sample_q<S, kDense>(v, cache, qe, Fs[e]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int src = group_lane<G>(lane, e % G);
+            Fs[e] = __shfl(Fs[e], src);
+            vs[e] = __shfl((int)vs[e], src) != 0;
+            ok = ok && vs[e];
+        }
+        g[0] = Fs[0] - Fs[1];
+        g[1] = Fs[2] - Fs[3];
+        g[2] = Fs[4] - Fs[5];
+    }
+    if (active && j == 0) {
+        float4 vout = make_float4(0.f, 0.f, 0.f, 0.f), nout = vout;
+        const float gl = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        if (ok && gl > 0.0f) {
+            vout = make_float4((float)(cam.t[0] + sh * r.d[0]), (float)(cam.t[1] + sh * r.d[1]),
+                               (float)(cam.t[2] + sh * r.d[2]), 1.0f);
+            nout = make_float4(g[0] / gl, g[1] / gl, g[2] / gl, 1.0f);
+        }
+        const size_t pix = (size_t)jpix * cam.width + i;
+        vertex[pix] = vout;
+        normal[pix] = nout;
+    }
+}
+
+}  // namespace tsdf

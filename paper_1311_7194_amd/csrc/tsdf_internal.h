@@ -31,6 +31,9 @@ static_assert(sizeof(DeviceState) == 256, "state line");
 
 // Event counters, spread over kCtrLanes addresses so that thousands of
 // wavefronts do not serialise on one atomic; the host sums the lanes.
+// Edge in pixels of the cells of the raycast's per-cell depth spans.
+constexpr int kCell = 2;
+
 constexpr int kCtrLanes = 256;
 enum { CTR_UPDATES = 0, CTR_FRESH = 1, CTR_NEW = 2, CTR_TOUCHED = 3, CTR_N = 4 };
 struct Counters {
@@ -46,6 +49,7 @@ struct VolumeView {
     uint32_t *pool_keys;        // capacity entries: key of the block in each pool slot
     uint32_t *block_min;        // capacity entries: ordered key of a lower bound of the block's non-chi T
     uint32_t *tile_range;       // raycast: per 8x8 pixel tile (min depth bits, max depth bits)
+    uint32_t *pix_range;        // raycast: per kCell x kCell pixel cell (min depth bits, max depth bits)
     uint32_t *occupancy;        // one bit per block of the virtual grid
     int32_t *block_index;       // optional dense index per virtual block: slot | positive << 30, -1 = empty
     uint32_t *cand_bits;        // per-frame candidate dedup bits (all clear between frames)
@@ -187,5 +191,13 @@ hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp
 hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
 hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,
                          hipStream_t s);
+
+// Host access to a volume for the batched path (volume.hip).  volume_view
+// returns the device pointers and sizes; volume_enqueue prepares a volume
+// for work that another path enqueues on `s` (remembers the stream, hands
+// out the next raycast stamp when `stamp` is non-null) and returns
+// TSDF_EFULL once a sticky device flag has been seen.
+VolumeView volume_view(const tsdf_volume *vol);
+tsdf_status volume_enqueue(tsdf_volume *vol, hipStream_t s, uint32_t *stamp);
 
 }  // namespace tsdf

@@ -115,7 +115,7 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // ------------------------------------------------------------ layout
 
 struct Layout {
-    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range,
+    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range, pix_range,
         poolT, poolP, total;
     uint64_t bitmap_words, tile_words, nblocks;
 };
@@ -174,6 +174,9 @@ static Layout layout_of(const tsdf_volume_desc *d)
     L.tile_words = (uint64_t)((d->max_width + 7) / 8) * (uint64_t)((d->max_height + 7) / 8);
     L.tile_range = off;
     off = align256(off + 8ull * L.tile_words);
+    L.pix_range = off;
+    off = align256(off + 8ull * (uint64_t)((d->max_width + kCell - 1) / kCell) *
+                             (uint64_t)((d->max_height + kCell - 1) / kCell));
     L.poolT = off;
     off = align256(off + elem * kBlockVoxels * (uint64_t)d->capacity_blocks);
     L.poolP = off;
@@ -208,6 +211,20 @@ struct tsdf_volume {
     double stage_ms[N_STAGES];
     uint64_t stage_launches[N_STAGES];
 };
+
+namespace tsdf {
+
+VolumeView volume_view(const tsdf_volume *vol) { return vol->view; }
+
+tsdf_status volume_enqueue(tsdf_volume *vol, hipStream_t s, uint32_t *stamp)
+{
+    if (vol->host_flags) return TSDF_EFULL;
+    vol->last_stream = s;
+    if (stamp) *stamp = ++vol->raycast_stamp == 0 ? ++vol->raycast_stamp : vol->raycast_stamp;
+    return TSDF_OK;
+}
+
+}  // namespace tsdf
 
 static hipEvent_t take_event(tsdf_volume *v)
 {
@@ -360,6 +377,7 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     w.pool_keys = (uint32_t *)(v->base + L.pool_keys);
     w.block_min = (uint32_t *)(v->base + L.block_min);
     w.tile_range = (uint32_t *)(v->base + L.tile_range);
+    w.pix_range = (uint32_t *)(v->base + L.pix_range);
     w.max_width = desc->max_width;
     w.max_height = desc->max_height;
     v->raycast_stamp = 0;

@@ -28,6 +28,9 @@ EXPORTED = [
     "tsdf_integrate_frame", "tsdf_raycast", "tsdf_query_stats", "tsdf_export_blocks",
     "tsdf_import_blocks", "tsdf_status_string", "tsdf_set_timing", "tsdf_read_timing",
     "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast",
+    "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
+    "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
+    "tsdf_batch_autotune_raycast",
 ]
 
 
@@ -104,8 +107,18 @@ def lib():
         L.tsdf_read_timing.argtypes = [P, P, ctypes.c_int32]
         L.tsdf_status_string.argtypes = [ctypes.c_int]
         L.tsdf_status_string.restype = ctypes.c_char_p
+        L.tsdf_batch_bytes.argtypes = [ctypes.c_int32]
+        L.tsdf_batch_bytes.restype = ctypes.c_uint64
+        L.tsdf_batch_create.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_uint64, P]
+        L.tsdf_batch_destroy.argtypes = [P]
+        L.tsdf_batch_destroy.restype = None
+        L.tsdf_batch_set_graph.argtypes = [P, ctypes.c_int32]
+        L.tsdf_batch_set_raycast_group.argtypes = [P, ctypes.c_int32]
+        L.tsdf_batch_get_raycast_group.argtypes = [P]
+        L.tsdf_batch_step.argtypes = [P, P, P, P, P, P, P]
+        L.tsdf_batch_autotune_raycast.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
         for name in EXPORTED:
-            if name not in ("tsdf_destroy_volume", "tsdf_status_string"):
+            if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -270,3 +283,94 @@ class Volume:
         n = keys.shape[0]
         _check(lib().tsdf_import_blocks(self.handle, _ptr(keys), _ptr(T), _ptr(P), n, stream_handle(stream)),
                "tsdf_import_blocks")
+
+
+class Batch:
+    """Several volumes advanced together by one batched step (fuse one frame
+    into each, then raycast each from the same pose).  Each scene's frame
+    size is fixed at creation; the step keeps per-scene vertex and normal
+    maps."""
+
+    def __init__(self, volumes: Sequence[Volume], Ks: Sequence, graph: bool = True):
+        n = len(volumes)
+        self.volumes = list(volumes)
+        self.K = [make_intrinsics(K) for K in Ks]
+        assert len(self.K) == n
+        dev = self.volumes[0].buffer.device
+        nbytes = int(lib().tsdf_batch_bytes(n))
+        if nbytes == 0:
+            raise TsdfError(EINVAL, "tsdf_batch_bytes")
+        self.table = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        handles = (ctypes.c_void_p * n)(*[v.handle.value for v in self.volumes])
+        intr = (Intrinsics * n)(*self.K)
+        h = ctypes.c_void_p()
+        _check(lib().tsdf_batch_create(handles, intr, n, _ptr(self.table), nbytes, ctypes.byref(h)),
+               "tsdf_batch_create")
+        self.handle = h
+        self.vertex = [torch.zeros((k.height, k.width, 4), dtype=torch.float32, device=dev) for k in self.K]
+        self.normal = [torch.zeros_like(v) for v in self.vertex]
+        self._vp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.vertex])
+        self._np = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.normal])
+        # graph capture needs a created stream; steps without an explicit one
+        # run on this stream, ordered after the caller's current stream
+        self.stream = torch.cuda.Stream(device=dev)
+        self.set_graph(graph)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().tsdf_batch_destroy(h)
+            self.handle = None
+
+    def set_graph(self, enable: bool):
+        _check(lib().tsdf_batch_set_graph(self.handle, 1 if enable else 0), "tsdf_batch_set_graph")
+
+    def set_raycast_group(self, group: int):
+        _check(lib().tsdf_batch_set_raycast_group(self.handle, int(group)), "tsdf_batch_set_raycast_group")
+
+    @property
+    def raycast_group(self) -> int:
+        return int(lib().tsdf_batch_get_raycast_group(self.handle))
+
+    def _poses(self, poses) -> np.ndarray:
+        arr = np.zeros((len(self.volumes), 12), np.float64)
+        for k, p in enumerate(poses):
+            if p is not None:
+                arr[k] = _pose_array(p)
+        return np.ascontiguousarray(arr)
+
+    def step(self, depths: Sequence[Optional[torch.Tensor]], poses, noise_kind: int = NOISE_QUADRATIC,
+             coeff: float = 0.0015, mlp_params: Optional[torch.Tensor] = None, stream=None):
+        """depths[k] None leaves scene k untouched this step."""
+        n = len(self.volumes)
+        assert len(depths) == n and len(poses) == n
+        dp = (ctypes.c_void_p * n)()
+        for k, d in enumerate(depths):
+            if d is not None:
+                assert d.is_cuda and d.dtype == torch.float32 and d.is_contiguous()
+                assert d.shape == (self.K[k].height, self.K[k].width)
+                dp[k] = d.data_ptr()
+        self._depths = list(depths)   # keep the inputs alive while the step runs
+        pa = self._poses(poses)
+        nm = NoiseModel(int(noise_kind), float(coeff),
+                        ctypes.c_void_p(mlp_params.data_ptr()) if mlp_params is not None else None)
+        own = stream is None
+        if own:
+            stream = self.stream
+            stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().tsdf_batch_step(self.handle, dp, pa.ctypes.data_as(ctypes.c_void_p), self._vp, self._np,
+                                     ctypes.byref(nm), stream_handle(stream)), "tsdf_batch_step")
+        if own:
+            torch.cuda.current_stream().wait_stream(stream)
+
+    def autotune_raycast(self, poses, reps: int = 3, stream=None):
+        pa = self._poses(poses)
+        best = ctypes.c_int32(0)
+        ms = ctypes.c_float(0)
+        if stream is None:
+            stream = self.stream
+            stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().tsdf_batch_autotune_raycast(self.handle, pa.ctypes.data_as(ctypes.c_void_p), self._vp,
+                                                 self._np, int(reps), stream_handle(stream), ctypes.byref(best),
+                                                 ctypes.byref(ms)), "tsdf_batch_autotune_raycast")
+        return int(best.value), float(ms.value)

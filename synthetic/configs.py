@@ -137,7 +137,8 @@ def c5_layout() -> List[dict]:
     for s in range(16):
         W, H = sizes[s % 3]
         vs = 3.0 / G[s]
-        cap = 1 << int(math.ceil(math.log2(max(4096, 450000 * (0.001 / vs) ** 2))))
+        # a 3 m ground plane plus objects: about 9e5 blocks at 1 mm, scaling with the area in blocks
+        cap = 1 << int(math.ceil(math.log2(max(4096, 900000 * (0.001 / vs) ** 2))))
         out.append(dict(G=G[s], vs=vs, W=W, H=H, frames=int(counts[s]), capacity=min(cap, 1 << 20)))
     return out
 

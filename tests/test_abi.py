@@ -96,3 +96,18 @@ def test_null_arguments_rejected(lib):
     assert lib.tsdf_raycast(None, None, None, None, None, None) == T.EINVAL
     assert lib.tsdf_query_stats(None, None) == T.EINVAL
     assert lib.tsdf_status_string(T.EFULL).decode().startswith("block pool")
+
+
+def test_batch_host_validation(lib):
+    assert lib.tsdf_batch_bytes(0) == 0
+    assert lib.tsdf_batch_bytes(65) == 0
+    assert lib.tsdf_batch_bytes(1) > 0 and lib.tsdf_batch_bytes(1) % 256 == 0
+    assert lib.tsdf_batch_bytes(16) >= lib.tsdf_batch_bytes(1)
+    h = ctypes.c_void_p()
+    assert lib.tsdf_batch_create(None, None, 1, None, 0, ctypes.byref(h)) == T.EINVAL
+    assert lib.tsdf_batch_create(None, None, 1, None, 0, None) == T.EINVAL
+    assert lib.tsdf_batch_step(None, None, None, None, None, None, None) == T.EINVAL
+    assert lib.tsdf_batch_set_graph(None, 1) == T.EINVAL
+    assert lib.tsdf_batch_set_raycast_group(None, 4) == T.EINVAL
+    assert lib.tsdf_batch_get_raycast_group(None) == 0
+    lib.tsdf_batch_destroy(None)

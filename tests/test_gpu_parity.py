@@ -80,10 +80,14 @@ def test_constant_variance_zero_q(tsdf):
     compare_volumes(gv, ov)
 
 
-@pytest.mark.parametrize("group,dense", [(8, True), (1, True), (16, True), (4, False), (2, True)])
-def test_raycast_of_imported_oracle_volume(tsdf, group, dense):
+@pytest.mark.parametrize("group,dense,close", [(8, True, False), (1, True, False), (16, True, False),
+                                               (4, False, False), (2, True, False), (4, True, True),
+                                               (8, False, True)])
+def test_raycast_of_imported_oracle_volume(tsdf, group, dense, close):
     """The oracle's volume copied into the GPU: raycasts must agree for every
-    ray group size, with the dense index and through the hash alone."""
+    ray group size, with the dense index and through the hash alone, from a
+    distant camera and from one close to the surfaces (blocks projecting to
+    hundreds of pixels)."""
     spec = small_orbit(width=96, height=72, n_frames=3, G=256, vs=0.008)
     ov = oracle_volume_for(spec)
     for k in range(3):
@@ -94,10 +98,54 @@ def test_raycast_of_imported_oracle_volume(tsdf, group, dense):
     gv.set_raycast_group(group)
     gv.import_blocks(torch.from_numpy(keys), torch.from_numpy(T).float(), torch.from_numpy(P).float())
     K = Intrinsics(110.0, 110.0, 60.3, 40.7, 121, 83)   # another camera, ragged size
-    pose = look_at((0.9, 0.6, -0.7), (0.0, 0.1, 0.0))
+    pose = look_at((0.35, 0.35, -0.35) if close else (0.9, 0.6, -0.7), (0.0, 0.1, 0.0))
     vert, nrm = gv.raycast(K, pose)
     torch.cuda.synchronize()
     ovv, onn, ofl = ov.raycast(Kvec(K), pose, K.width, K.height, n_threads=8)
     rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, spec.grid.voxel_size)
-    print(f"[parity] imported raycast G={group} dense={dense}", rs, flush=True)
+    print(f"[parity] imported raycast G={group} dense={dense} close={close}", rs, flush=True)
     assert rs["hits"] > 1000
+
+
+def test_raycast_bitwise_independent_of_group_and_index(tsdf):
+    """Group size and index mode change the speed of the raycast, never its
+    maps: every (group, index) pair gives bitwise the same vertex and normal
+    maps, here with blocks close to the camera (large projected footprints)."""
+    spec = small_orbit(width=96, height=72, n_frames=3, G=256, vs=0.008)
+    ov = oracle_volume_for(spec)
+    for k in range(3):
+        d, p = sequence_frame(spec, k)
+        ov.integrate(d.numpy(), Kvec(spec.K), p)
+    keys, T, P = ov.export()
+    K = Intrinsics(150.0, 150.0, 63.5, 47.5, 127, 95)
+    poses = [look_at((0.9, 0.6, -0.7), (0.0, 0.1, 0.0)), look_at((0.35, 0.35, -0.35), (0.0, 0.1, 0.0))]
+    # visible blocks must include both small projections (per-pixel spans) and
+    # ones spanning over 256 pixels (per-tile spans)
+    g = spec.grid
+    corners = np.array([[dx, dy, dz] for dx in (0, 1) for dy in (0, 1) for dz in (0, 1)], np.float64)
+    box = np.asarray(g.origin) + (8.0 * keys[:, None, :] + 0.5 + 8.0 * corners[None]) * g.voxel_size
+    small = large = 0
+    for pose in poses:
+        xc = (box - pose[:, 3]) @ pose[:, :3]
+        front = (xc[..., 2] > 0.05).all(1)
+        u = K.fx * xc[..., 0] / xc[..., 2] + K.cx
+        w = K.fy * xc[..., 1] / xc[..., 2] + K.cy
+        vis = front & (u.max(1) > 0) & (u.min(1) < K.width) & (w.max(1) > 0) & (w.min(1) < K.height)
+        span = (u.max(1) - u.min(1) + 3) * (w.max(1) - w.min(1) + 3)
+        small += int((vis & (span < 200)).sum())
+        large += int((vis & (span > 300)).sum())
+    assert small > 100 and large > 100, (small, large)
+    ref = None
+    for dense in (True, False):
+        gv = gpu_volume_for(spec, max_wh=(128, 96), dense_index=dense)
+        gv.import_blocks(torch.from_numpy(keys), torch.from_numpy(T).float(), torch.from_numpy(P).float())
+        for group in (1, 2, 4, 8, 16):
+            gv.set_raycast_group(group)
+            maps = [gv.raycast(K, pose) for pose in poses]
+            torch.cuda.synchronize()
+            maps = [(v.cpu(), n.cpu()) for v, n in maps]
+            if ref is None:
+                ref = maps
+                assert all(int((v[..., 3] > 0).sum()) > 300 for v, _ in maps)
+            for (v, n), (rv, rn) in zip(maps, ref):
+                assert torch.equal(v, rv) and torch.equal(n, rn), (group, dense)
