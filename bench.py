@@ -120,10 +120,10 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
         updates=st["total_updates"], new_blocks=st["total_new_blocks"], candidates=st["total_candidates"],
         touched_blocks=st["total_touched_blocks"],
         allocated_blocks=st["allocated_blocks"], status_flags=st["status_flags"],
-        prep_ms=tm["prep_ms"], fuse_ms=tm["fuse_ms"], raycast_ms=tm["raycast_ms"],
+        prep_ms=tm["prep_ms"], fuse_ms=tm["fuse_ms"], range_ms=tm["range_ms"], raycast_ms=tm["raycast_ms"],
         step_ms=e0.elapsed_time(e1) / steps, wall_s=wall, last_frame_hits=hits, raycast_group=group,
         voxel_updates_per_s=st["total_updates"] / (integ_ms * 1e-3),
-        raycast_mpix_s=pixels / (tm["raycast_ms"] * 1e-3) / 1e6,
+        raycast_mpix_s=pixels / ((tm["range_ms"] + tm["raycast_ms"]) * 1e-3) / 1e6,
     )
     fb = fuse_bytes(st, elem, pixels)
     res["fuse_bytes"] = fb
@@ -131,11 +131,48 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
     res["fuse_avg_us"] = tm["fuse_ms"] * 1e3 / max(tm["fuse_launches"], 1)
     res["raycast_avg_us"] = tm["raycast_ms"] * 1e3 / max(tm["raycast_launches"], 1)
     res["prep_avg_us"] = tm["prep_ms"] * 1e3 / max(tm["prep_launches"], 1)
+    res["range_avg_us"] = tm["range_ms"] * 1e3 / max(tm["range_launches"], 1)
     # raycast algorithmic bytes counted as its output only (32 B per pixel): a lower bound
     res["raycast_gbs_output_only"] = 32 * pixels / (tm["raycast_ms"] * 1e-3) / 1e9
     res["_vol"] = vol
     res["_frames"] = (depths, poses)
     return res
+
+
+KERNEL_SOURCES = ("fuse_device.h", "fuse.hip", "raycast_device.h", "raycast.hip", "tsdf_internal.h",
+                  "mlp_device.h", "mlp_features.h", "volume.hip")
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources of the fusion and raycast kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1311_7194_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src, table = None, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("kernel_source_sha256:"):
+            src = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic|"):
+            _, k, w, nbytes = line.split("|")
+            table[(k, w)] = float(nbytes)
+    if src != kernel_source_hash():
+        return None
+    return table.get((kernel, workload))
 
 
 def roofline_of(res):
@@ -144,12 +181,14 @@ def roofline_of(res):
         launches = res["frames"]
         per_launch = res["fuse_bytes"] / launches
         achieved = res["fuse_gbs"]
+        t = profiled_traffic("fuse_kernel", f"{res['workload']}/{res['storage']}")
         return dict(kernel="fuse_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=t,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(res["fuse_avg_us"], 2))
     achieved = res["raycast_gbs_output_only"]
+    t = profiled_traffic("raycast_kernel", f"{res['workload']}/{res['storage']}")
     return dict(kernel="raycast_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5), traffic=t,
                 bytes_per_launch=32 * res["width"] * res["height"], avg_launch_us=round(res["raycast_avg_us"], 2))
 
 
@@ -347,7 +386,7 @@ def main():
                    "storage": res["storage"], "parallelism": "single-gpu"},
         "raycast_mpix_s": round(res["raycast_mpix_s"], 2),
         "stage_us_per_frame": {"prep": round(res["prep_avg_us"], 2), "fuse": round(res["fuse_avg_us"], 2),
-                               "raycast": round(res["raycast_avg_us"], 2)},
+                               "range": round(res["range_avg_us"], 2), "raycast": round(res["raycast_avg_us"], 2)},
         "updates_per_frame": res["updates"] // args.steps,
         "raycast_group": res["raycast_group"],
         "roofline": roofline_of(res),

@@ -68,7 +68,7 @@ typedef struct {
     double voxel_size;         /* metres */
     double origin[3];          /* world position of the grid's min corner, metres */
     double trunc_voxels;       /* delta = trunc_voxels * voxel_size */
-    uint32_t capacity_blocks;  /* block pool size */
+    uint32_t capacity_blocks;  /* block pool size, 1 .. 2^22 */
     uint32_t hash_slots;       /* power of two >= 2 * capacity_blocks */
     int32_t storage;           /* tsdf_storage: T_hat and P_hat as float32 or float16 */
     double q_hat;              /* process variance Q / delta^2 (Algorithm 3) */
@@ -115,10 +115,11 @@ typedef struct {
 } tsdf_stats;
 
 /* Per-stage kernel times from HIP events recorded around each launch while
- * timing is enabled (pixel preparation, block fusion, raycast). */
+ * timing is enabled: pixel preparation, block fusion, the raycast's range
+ * pass (span reset and per-block projection) and the raycast march itself. */
 typedef struct {
-    double prep_ms, fuse_ms, raycast_ms;
-    uint64_t prep_launches, fuse_launches, raycast_launches;
+    double prep_ms, fuse_ms, range_ms, raycast_ms;
+    uint64_t prep_launches, fuse_launches, range_launches, raycast_launches;
 } tsdf_timing;
 
 typedef struct tsdf_volume tsdf_volume;

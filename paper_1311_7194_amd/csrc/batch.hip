@@ -23,6 +23,7 @@ constexpr int kMaxScenes = 64;
 struct SceneDesc {
     VolumeView v;
     Camera cam;
+    FuseCam fc;
     NoiseParams noise;
     const float *depth;
     float4 *vertex;
@@ -110,8 +111,7 @@ __global__ __launch_bounds__(256) void batch_fuse(const SceneDesc *__restrict__ 
             cur = s;
         }
         const SceneDesc &d = sd[s];
-        const CamF cf{(float)d.cam.fx, (float)d.cam.fy, (float)d.cam.cx, (float)d.cam.cy};
-        fuse_block<S>(d.v, d.cam, cf, d.v.cand_list[g - pre[s]], lane, acc);
+        fuse_block<S>(d.v, d.cam, d.fc, d.v.cand_list[g - pre[s]], lane, acc);
     }
     if (cur >= 0) fuse_flush(sd[cur].v, acc, wave, lane);
 }
@@ -262,6 +262,7 @@ static tsdf_status stage_step(tsdf_batch *b, const float *const *depth_dev, cons
             for (int c = 0; c < 3; ++c) d.cam.R[3 * r + c] = p[4 * r + c];
             d.cam.t[r] = p[4 * r + 3];
         }
+        d.fc = make_fuse_cam(d.v, d.cam);
         d.depth = depth_dev ? depth_dev[k] : nullptr;
         d.vertex = (float4 *)vertex_dev[k];
         d.normal = (float4 *)normal_dev[k];

@@ -48,16 +48,21 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam)
+__global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam, FuseCam fc)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * 4u;
     const uint32_t ncand = min(v.state->cand_count, v.max_candidates);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&v.state->total_candidates, (unsigned long long)ncand);
-    const CamF cf{(float)cam.fx, (float)cam.fy, (float)cam.cx, (float)cam.cy};
     FuseAcc acc;
-    for (uint32_t c = wave; c < ncand; c += nwaves) fuse_block<S>(v, cam, cf, v.cand_list[c], lane, acc);
+    // the next candidate's key is loaded one block ahead
+    uint32_t key = wave < ncand ? v.cand_list[wave] : 0u;
+    for (uint32_t c = wave; c < ncand; c += nwaves) {
+        const uint32_t next = c + nwaves < ncand ? v.cand_list[c + nwaves] : 0u;
+        fuse_block<S>(v, cam, fc, key, lane, acc);
+        key = next;
+    }
     fuse_flush(v, acc, wave, lane);
 }
 
@@ -67,10 +72,11 @@ hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s)
     uint32_t want = (v.max_candidates + 3) / 4;
     uint32_t blocks = want < 4096u ? want : 4096u;
     if (blocks == 0) blocks = 1;
+    const FuseCam fc = make_fuse_cam(v, cam);
     if (v.storage == TSDF_F16)
-        hipLaunchKernelGGL(fuse_kernel<__half>, dim3(blocks), dim3(256), 0, s, v, cam);
+        hipLaunchKernelGGL(fuse_kernel<__half>, dim3(blocks), dim3(256), 0, s, v, cam, fc);
     else
-        hipLaunchKernelGGL(fuse_kernel<float>, dim3(blocks), dim3(256), 0, s, v, cam);
+        hipLaunchKernelGGL(fuse_kernel<float>, dim3(blocks), dim3(256), 0, s, v, cam, fc);
     return hipGetLastError();
 }
 

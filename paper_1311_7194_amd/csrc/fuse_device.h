@@ -208,32 +208,61 @@ __device__ __forceinline__ void prep_body(const VolumeView &v, const float *__re
 
 // ---------------------------------------------------------------- fuse
 
-// Camera parameters in float for the pixel-index filter.
-struct CamF {
-    float fx, fy, cx, cy;
+// Per-frame constants of the voxel projection.  Along a lane's voxel column
+// (grid z) the camera coordinates advance by R^T (0, 0, voxel): the decisions
+// start from the exact coordinates of the column's first voxel plus z times
+// that step, which differs from the defined double expression by at most
+// `err` metres; the decisions below are taken only where that difference
+// cannot change them, otherwise the defined expression is evaluated.
+struct FuseCam {
+    double sx, sy, sz;   // camera-frame step per voxel along grid z
+    double err;          // bound on |approximate - defined| camera coordinate
+    double ceu, cev;     // pixel margin: r * ce + cr, r = 1 / z_c
+    double cru, crv;
+    double thr_s;        // |s| within thr_s of delta: decided by the defined expression
 };
 
-// Nearest-pixel index of a voxel from its camera coordinates (Section 7.1,
-// projective measurement).  The index is first found in float; the result
-// is returned only when the float value lies farther from a rounding
-// boundary than its proven error bound, so it equals the index of the
-// defined double expression.  Returns the linear pixel index, -1 when the
-// voxel falls outside the image, -2 when the double expression must decide.
-__device__ __forceinline__ int pixel_filter(const Camera &cam, const CamF &cf, double xc, double yc, double zc)
+__host__ __device__ inline FuseCam make_fuse_cam(const VolumeView &v, const Camera &cam)
 {
-#pragma clang fp contract(off)
-    if (!(zc > 0.0)) return -1;
-    const float xf = (float)xc, yf = (float)yc, zf = (float)zc;
-    const float rz = __builtin_amdgcn_rcpf(zf);
-    const float au = cf.fx * xf * rz, av = cf.fy * yf * rz;
-    const float uf = au + cf.cx, vf = av + cf.cy;
-    const float fu = floorf(uf + 0.5f), fv = floorf(vf + 0.5f);
-    // |u_float - u_exact| <= 4.2e-7 |fx x/z| + 6e-8 |cx| + 1.2e-7 |u|; the margin is 4x that
-    const float eu = 2e-6f * (fabsf(au) + fabsf(cf.cx) + fabsf(uf)) + 1e-6f;
-    const float ev = 2e-6f * (fabsf(av) + fabsf(cf.cy) + fabsf(vf)) + 1e-6f;
-    const float du = uf + 0.5f - fu, dv = vf + 0.5f - fv;
-    if (!(du > eu && du < 1.0f - eu && dv > ev && dv < 1.0f - ev)) return -2;
-    if (!(fu >= 0.0f && fu < (float)cam.width && fv >= 0.0f && fv < (float)cam.height)) return -1;
+    FuseCam f;
+    f.sx = cam.R[6] * v.vs;
+    f.sy = cam.R[7] * v.vs;
+    f.sz = cam.R[8] * v.vs;
+    // magnitude bound of every intermediate (positions, differences, camera coordinates)
+    double m = 0.0, mt = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        m = fmax(m, fabs(v.origin[a]) + (double)v.dims[a] * v.vs);
+        mt = fmax(mt, fabs(cam.t[a]));
+    }
+    const double M = 3.0 * (m + mt) + 1.0;
+    const double ulp = 1.1102230246251565e-16;   // 2^-53
+    f.err = 192.0 * ulp * M;
+    // |u~ - u| <= (fx + |a_u|) err / z_c + rounding, with |a_u| <= W + 2 + |c_x|
+    // wherever the decision can be near a pixel boundary inside the image
+    const double au = cam.width + 2.0 + fabs(cam.cx), av = cam.height + 2.0 + fabs(cam.cy);
+    f.ceu = 2.0 * f.err * (cam.fx + au);
+    f.cev = 2.0 * f.err * (cam.fy + av);
+    f.cru = 64.0 * ulp * au + 1e-300;
+    f.crv = 64.0 * ulp * av + 1e-300;
+    f.thr_s = 4.0 * f.err + 64.0 * ulp * M;
+    return f;
+}
+
+// Nearest-pixel index from approximate camera coordinates (within fc.err of
+// the defined ones): the linear pixel index, -1 outside the image or behind
+// the camera, -2 when only the defined expression can decide.
+__device__ __forceinline__ int pixel_filter(const Camera &cam, const FuseCam &fc, double xc, double yc, double zc)
+{
+    if (!(zc > 2.0 * fc.err)) return zc < -2.0 * fc.err ? -1 : -2;
+    double r = __builtin_amdgcn_rcp(zc);
+    r = fma(r, fma(-zc, r, 1.0), r);   // two Newton steps: r = 1/z_c to a few ulp
+    r = fma(r, fma(-zc, r, 1.0), r);
+    const double tu = fma(cam.fx * xc, r, cam.cx + 0.5), tv = fma(cam.fy * yc, r, cam.cy + 0.5);
+    const double fu = floor(tu), fv = floor(tv);
+    const double du = tu - fu, dv = tv - fv;
+    const double eu = fma(r, fc.ceu, fc.cru), ev = fma(r, fc.cev, fc.crv);
+    if (!(du > eu && du < 1.0 - eu && dv > ev && dv < 1.0 - ev)) return -2;
+    if (!(fu >= 0.0 && fu < (double)cam.width && fv >= 0.0 && fv < (double)cam.height)) return -1;
     return (int)fv * cam.width + (int)fu;
 }
 
@@ -257,10 +286,12 @@ __device__ __forceinline__ void kalman(float &T, float &P, float Tk, float pk, f
         T = Tk;
         P = pk;
     } else {
+        // K = P / (P + p_k); the new variance (1 - K) P is formed as K p_k,
+        // which is the same quantity without the cancellation in 1 - K
         P = P + q;
-        const float K = P / (P + pk);
+        const float K = P * __builtin_amdgcn_rcpf(P + pk);
         T = T + K * (Tk - T);
-        P = (1.0f - K) * P;
+        P = K * pk;
     }
     if (fabsf(T) > 1.0f) T = kChi;
 }
@@ -293,7 +324,7 @@ struct FuseAcc {
 
 // One candidate block, processed by one wavefront (all 64 lanes).
 template <typename S>
-__device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &cam, const CamF &cf, uint32_t key,
+__device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &cam, const FuseCam &fc, uint32_t key,
                                            int lane, FuseAcc &acc)
 {
     const int lx = lane & 7, ly = lane >> 3;
@@ -302,6 +333,10 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
     S *__restrict__ poolP = (S *)v.poolP;
     int bx, by, bz;
     unpack_key(key, bx, by, bz);
+    // first probe of the block's hash chain, issued before the decisions so
+    // that its latency overlaps them (only this wavefront inserts this key)
+    unsigned long long first_entry = 0;
+    if (lane == 0) first_entry = v.hash[hash_key(key) & v.hash_mask];
     // x_c = R^T (x - t) = (R00 dx + R10 dy) + R20 dz: the bracket is the
     // lane's (x, y) part, the last term varies with z
     double ax, ay, az;
@@ -315,40 +350,43 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
         ay = cam.R[1] * dx + cam.R[4] * dy;
         az = cam.R[2] * dx + cam.R[5] * dy;
     }
+    // the defined camera coordinates of the column's first voxel (z = 0)
+    double x0, y0, z0;
+    {
+#pragma clang fp contract(off)
+        const double pz = v.origin[2] + ((double)(bz * 8) + 0.5) * v.vs;
+        const double dz = pz - cam.t[2];
+        x0 = ax + cam.R[6] * dz;
+        y0 = ay + cam.R[7] * dz;
+        z0 = az + cam.R[8] * dz;
+    }
     float Tk[8], pk[8];
     uint32_t vmask = 0;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-        // phase 1: camera coordinates (exact doubles) and the float pixel filter
-        double zcs[4];
+        // phase 1: approximate camera coordinates and the pixel decision
         int pix[4];
-        int need_exact = 0;
+        int exact = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int z = 4 * half + k;
-            double xc, yc, zc;
-            {
-#pragma clang fp contract(off)
-                const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
-                const double dz = pz - cam.t[2];
-                xc = ax + cam.R[6] * dz;
-                yc = ay + cam.R[7] * dz;
-                zc = az + cam.R[8] * dz;
-            }
-            zcs[k] = zc;
-            pix[k] = pixel_filter(cam, cf, xc, yc, zc);
-            need_exact |= (pix[k] == -2) << k;
+            const double zf = (double)(4 * half + k);
+            const double xc = fma(zf, fc.sx, x0), yc = fma(zf, fc.sy, y0), zc = fma(zf, fc.sz, z0);
+            pix[k] = pixel_filter(cam, fc, xc, yc, zc);
+            exact |= (pix[k] == -2) << k;
         }
-        // phase 2 (rare): voxels near a pixel boundary take the double expression
-        if (need_exact) {
+        // phase 2 (rare): voxels the approximation cannot decide take the
+        // defined expression
+        if (exact) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if ((need_exact >> k) & 1) {
+                if ((exact >> k) & 1) {
 #pragma clang fp contract(off)
                     const double pz = v.origin[2] + ((double)(bz * 8 + 4 * half + k) + 0.5) * v.vs;
                     const double dz = pz - cam.t[2];
-                    pix[k] = pixel_exact(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
-                                         ax + cam.R[6] * dz, ay + cam.R[7] * dz, zcs[k]);
+                    const double zc = az + cam.R[8] * dz;
+                    pix[k] = zc > 0.0 ? pixel_exact(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height,
+                                                    ax + cam.R[6] * dz, ay + cam.R[7] * dz, zc)
+                                      : -1;
                 }
             }
         }
@@ -356,11 +394,18 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
         float2 pm[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) pm[k] = pixmap[pix[k] >= 0 ? pix[k] : 0];
-        // phase 4: s = D - z_c in double, |s| <= delta
+        // phase 4: s = D - z_c, |s| <= delta; the defined z_c where the
+        // pixel needed it or s lies near the threshold
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int z = 4 * half + k;
-            const double sd = (double)pm[k].x - zcs[k];
+            double sd = (double)pm[k].x - fma((double)z, fc.sz, z0);
+            if (((exact >> k) & 1) || fabs(fabs(sd) - v.delta) <= fc.thr_s) {
+#pragma clang fp contract(off)
+                const double pz = v.origin[2] + ((double)(bz * 8 + z) + 0.5) * v.vs;
+                const double dz = pz - cam.t[2];
+                sd = (double)pm[k].x - (az + cam.R[8] * dz);
+            }
             const bool ok = pix[k] >= 0 && pm[k].x > 0.0f && fabs(sd) <= v.delta;
             Tk[z] = (float)(sd * v.inv_delta);
             pk[z] = pm[k].y;
@@ -377,7 +422,8 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
     int32_t slot = -1;
     int fresh = 0;
     if (lane == 0) {
-        slot = hash_find(v, key);
+        const uint32_t k0 = (uint32_t)(first_entry & 0xffffffffu);
+        slot = k0 == key ? (int32_t)(first_entry >> 32) : k0 == kEmptyKey ? -1 : hash_find(v, key);
         if (slot < 0) {
             slot = hash_insert_unique(v, key);
             if (slot >= 0) {

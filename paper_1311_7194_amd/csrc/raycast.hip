@@ -9,13 +9,14 @@
 //
 // Range shrinking.  The paper rasterises the faces of occupied blocks into
 // per-pixel start and end textures so that rays only traverse the depth span
-// of occupied blocks.  Here a compute pass does the same: for every
-// allocated block it projects the box in which that block is the base of the
-// interpolation stencil and widens the [min, max] camera depth of every pixel
-// whose centre the box's projection may cover (blocks whose projection spans
-// more than 256 pixels widen whole 8x8 tiles instead).  Every valid sample
-// lies in such a box, so starting and ending each ray at its pixel's span
-// (joined with its tile's) skips only invalid samples.
+// of occupied blocks.  Here a compute pass does the same at the granularity
+// of 4x4-pixel cells: for every allocated block it projects the box in which
+// that block is the base of the interpolation stencil and widens the
+// [min, max] camera depth of every cell holding a pixel centre the box's
+// projection may cover (blocks whose projection spans more than 64 cells
+// widen whole 8x8-pixel tiles instead).  Every valid sample lies in such a
+// box, so starting and ending each ray at its cell's span (joined with its
+// tile's) skips only invalid samples.
 //
 // March.  A group of G lanes marches one ray: lane j evaluates sample
 // n_base + j, shuffles pair every sample with its predecessor and a ballot
@@ -65,8 +66,7 @@ static void launch_group(int G, dim3 grid, hipStream_t s, const VolumeView &v, c
     }
 }
 
-hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
-                          float4 *normal, hipStream_t s)
+hipError_t launch_range(const VolumeView &v, const Camera &cam, uint32_t stamp, hipStream_t s)
 {
     const int tiles_x = (cam.width + kRT - 1) / kRT, tiles_y = (cam.height + kRT - 1) / kRT;
     const int n_tiles = tiles_x * tiles_y;
@@ -74,10 +74,15 @@ hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp
                        cam.width, cam.height);
     // range pass over the allocated blocks (grid-stride; the block count stays on the device)
     hipLaunchKernelGGL(range_kernel, dim3(2048), dim3(256), 0, s, v, cam, stamp, tiles_x, tiles_y);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_march(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
+                        float4 *normal, hipStream_t s)
+{
+    const int tiles_x = (cam.width + kRT - 1) / kRT, tiles_y = (cam.height + kRT - 1) / kRT;
     const int G = (group == 1 || group == 2 || group == 4 || group == 16) ? group : 8;
-    const long long threads = (long long)n_tiles * 64 * G;
+    const long long threads = (long long)tiles_x * tiles_y * 64 * G;
     dim3 grid((unsigned)((threads + 255) / 256));
     const bool dense = v.block_index != nullptr;
     if (v.storage == TSDF_F16) {

@@ -10,6 +10,8 @@ namespace tsdf {
 constexpr int kRT = 8;                      // raycast tile edge in pixels
 constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
 constexpr int kCellFootprint = 64;          // largest footprint (cells) a block widens cell by cell
+constexpr uint32_t kInfoEmpty = 1u << 30;    // march: the sample's cell block is absent
+constexpr uint32_t kInfoPositive = 1u << 31; // march: every value the cell's stencils reach is positive
 
 // ------------------------------------------------------------ range maps
 
@@ -103,8 +105,8 @@ __device__ __forceinline__ void range_block(const VolumeView &v, const Camera &c
         for (int d = d0; d <= d1; ++d)
             for (int c = c0; c <= c1; ++c) {
                 const size_t p = (size_t)d * cw + c;
-                if (cmin[p] > zl) atomicMin(&cmin[p], zl);
-                if (cmax[p] < zh) atomicMax(&cmax[p], zh);
+                atomicMin(&cmin[p], zl);   // no return value: the lane does not wait
+                atomicMax(&cmax[p], zh);
             }
         return;
     }
@@ -133,12 +135,15 @@ __device__ __forceinline__ float ld<float>(const float *p) { return *p; }
 template <>
 __device__ __forceinline__ float ld<__half>(const __half *p) { return __half2float(*p); }
 
-// Cached slots of cell block B and its upper neighbours B + {0,1}^3, and
+// Pool element offsets (slot * 512) of cell block B and its upper
+// neighbours B + {0,1}^3; absent blocks point at the pool's chi block, so a
+// stencil reaching them reads chi and is invalid without a branch.  Also
 // whether every non-chi value in those 8 blocks is positive (then no sample
 // of the cell can have F <= 0: F is a convex combination of them).
 struct SlotCache {
     int B[3];
-    int32_t s[8];
+    uint32_t base[8];
+    bool empty;      // block B itself is absent
     bool positive;
 };
 
@@ -149,15 +154,28 @@ __device__ __forceinline__ void fill_cache(const VolumeView &v, SlotCache &c, in
     c.B[0] = bx;
     c.B[1] = by;
     c.B[2] = bz;
+    const uint32_t chi_base = v.capacity * (uint32_t)kBlockVoxels;
     bool pos = true;
     if constexpr (kDense) {
+        // B itself is inside the grid (its stencils are); neighbours may not
+        // be: those read B's own entry and are then taken as absent
+        const uint32_t n0 = (uint32_t)v.nblk[0], n01 = n0 * (uint32_t)v.nblk[1];
+        const uint32_t lin = (uint32_t)block_linear(v, bx, by, bz);
+        const bool inx = bx + 1 < v.nblk[0], iny = by + 1 < v.nblk[1], inz = bz + 1 < v.nblk[2];
+        int32_t raw[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int x = bx + (k & 1), y = by + ((k >> 1) & 1), z = bz + ((k >> 2) & 1);
-            const bool in = x < v.nblk[0] && y < v.nblk[1] && z < v.nblk[2];
-            const int32_t e = in ? v.block_index[block_linear(v, x, y, z)] : -1;
-            c.s[k] = e < 0 ? -1 : (e & kIndexSlotMask);
+            const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
+            const uint32_t nb = lin + (in ? (k & 1) + ((k & 2) ? n0 : 0u) + ((k & 4) ? n01 : 0u) : 0u);
+            raw[k] = v.block_index[nb];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
+            const int32_t e = in ? raw[k] : -1;
+            c.base[k] = e < 0 ? chi_base : (uint32_t)(e & kIndexSlotMask) * (uint32_t)kBlockVoxels;
             pos &= (e < 0) || (e & kIndexPositive);
+            if (k == 0) c.empty = e < 0;
         }
     } else {
         uint32_t kmin = kKeyPosInf;
@@ -167,45 +185,83 @@ __device__ __forceinline__ void fill_cache(const VolumeView &v, SlotCache &c, in
             int32_t sl = -1;
             if (x < v.nblk[0] && y < v.nblk[1] && z < v.nblk[2] && occupied(v, x, y, z))
                 sl = hash_find(v, pack_key(x, y, z));
-            c.s[k] = sl;
+            c.base[k] = sl < 0 ? chi_base : (uint32_t)sl * (uint32_t)kBlockVoxels;
             if (sl >= 0) kmin = min(kmin, v.block_min[sl]);
+            if (k == 0) c.empty = sl < 0;
         }
         pos = kmin > kKeyZero;
     }
     c.positive = pos;
 }
 
+// The march's refill, without control flow around the cache: only the
+// index loads are conditional on `need`, the cache takes the new entries by
+// selection (a loop-carried cache updated inside a branch is copied on every
+// iteration).  Dense index only.
+__device__ __forceinline__ void refill_dense(const VolumeView &v, SlotCache &c, bool need, int bx, int by, int bz)
+{
+    const uint32_t n0 = (uint32_t)v.nblk[0], n01 = n0 * (uint32_t)v.nblk[1];
+    const uint32_t lin = (uint32_t)block_linear(v, bx, by, bz);
+    const bool inx = bx + 1 < v.nblk[0], iny = by + 1 < v.nblk[1], inz = bz + 1 < v.nblk[2];
+    int32_t raw[8];
+    if (need) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
+            raw[k] = v.block_index[lin + (in ? (k & 1) + ((k & 2) ? n0 : 0u) + ((k & 4) ? n01 : 0u) : 0u)];
+        }
+    }
+    const uint32_t chi_base = v.capacity * (uint32_t)kBlockVoxels;
+    bool pos = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
+        const int32_t e = in ? raw[k] : -1;
+        pos &= (e < 0) || (e & kIndexPositive);
+        const uint32_t b = e < 0 ? chi_base : (uint32_t)(e & kIndexSlotMask) * (uint32_t)kBlockVoxels;
+        c.base[k] = need ? b : c.base[k];
+        if (k == 0) c.empty = need ? e < 0 : c.empty;
+    }
+    c.positive = need ? pos : c.positive;
+    c.B[0] = need ? bx : c.B[0];
+    c.B[1] = need ? by : c.B[1];
+    c.B[2] = need ? bz : c.B[2];
+}
+
 // Trilinear F at integer base c (global voxel indices) with fractions f,
-// using slots from the cache (c must lie in cell c.B).  False when invalid.
+// using offsets from the cache (c must lie in cell c.B).  False when invalid.
 template <typename S>
 __device__ __forceinline__ bool interp_cached(const VolumeView &v, const SlotCache &cache, const int c[3],
                                               const float f[3], float &F)
 {
-    const S *pool = (const S *)v.poolT;
-    const int l0 = c[0] & 7, l1 = c[1] & 7, l2 = c[2] & 7;
-    float val[8];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
-        const int sx = (l0 + ox) >> 3, sy = (l1 + oy) >> 3, sz = (l2 + oz) >> 3;
-        const int sel = sx | (sy << 1) | (sz << 2);
-        int32_t slot = cache.s[0];
-#pragma unroll
-        for (int m = 1; m < 8; ++m) slot = (sel == m) ? cache.s[m] : slot;
-        const int vx = (l0 + ox) & 7, vy = (l1 + oy) & 7, vz = (l2 + oz) & 7;
-        const float T = slot >= 0 ? ld(pool + (size_t)slot * kBlockVoxels + vx + 8 * vy + 64 * vz) : kChi;
-        ok &= fabsf(T) <= 1.0f;
-        val[k] = T;
-    }
-    const float x00 = val[0] + f[0] * (val[1] - val[0]);
-    const float x10 = val[2] + f[0] * (val[3] - val[2]);
-    const float x01 = val[4] + f[0] * (val[5] - val[4]);
-    const float x11 = val[6] + f[0] * (val[7] - val[6]);
-    const float y0 = x00 + f[1] * (x10 - x00);
-    const float y1 = x01 + f[1] * (x11 - x01);
-    F = y0 + f[2] * (y1 - y0);
-    return ok;
+    const S *__restrict__ pool = (const S *)v.poolT;
+    const uint32_t l0 = c[0] & 7, l1 = c[1] & 7, l2 = c[2] & 7;
+    // the stencil's upper neighbour leaves the block along an axis only from local index 7
+    const bool cx = l0 == 7, cy = l1 == 7, cz = l2 == 7;
+    const uint32_t x0 = l0, x1 = cx ? 0u : l0 + 1u;
+    const uint32_t y0 = 8u * l1, y1 = cy ? 0u : y0 + 8u;
+    const uint32_t z0 = 64u * l2, z1 = cz ? 0u : z0 + 64u;
+    // block of each corner (x fastest): select along x, then y, then z
+    const uint32_t *b = cache.base;
+    const uint32_t b0 = b[0], b1 = cx ? b[1] : b0;
+    const uint32_t b2 = cy ? b[2] : b0, b3 = cy ? (cx ? b[3] : b[2]) : b1;
+    const uint32_t t45 = cx ? b[5] : b[4], t67 = cx ? b[7] : b[6];
+    const uint32_t b4 = cz ? b[4] : b0, b5 = cz ? t45 : b1;
+    const uint32_t b6 = cz ? (cy ? b[6] : b[4]) : b2, b7 = cz ? (cy ? t67 : t45) : b3;
+    const float v0 = ld(pool + (b0 + x0 + y0 + z0)), v1 = ld(pool + (b1 + x1 + y0 + z0));
+    const float v2 = ld(pool + (b2 + x0 + y1 + z0)), v3 = ld(pool + (b3 + x1 + y1 + z0));
+    const float v4 = ld(pool + (b4 + x0 + y0 + z1)), v5 = ld(pool + (b5 + x1 + y0 + z1));
+    const float v6 = ld(pool + (b6 + x0 + y1 + z1)), v7 = ld(pool + (b7 + x1 + y1 + z1));
+    const float m = fmaxf(fmaxf(fmaxf(fabsf(v0), fabsf(v1)), fmaxf(fabsf(v2), fabsf(v3))),
+                          fmaxf(fmaxf(fabsf(v4), fabsf(v5)), fmaxf(fabsf(v6), fabsf(v7))));
+    const float x00 = v0 + f[0] * (v1 - v0);
+    const float x10 = v2 + f[0] * (v3 - v2);
+    const float x01 = v4 + f[0] * (v5 - v4);
+    const float x11 = v6 + f[0] * (v7 - v6);
+    const float y0f = x00 + f[1] * (x10 - x00);
+    const float y1f = x01 + f[1] * (x11 - x01);
+    F = y0f + f[2] * (y1f - y0f);
+    return m <= 1.0f;
 }
 
 __device__ __forceinline__ void q_at(const Ray &r, double s, double q[3])
@@ -242,7 +298,12 @@ __device__ __forceinline__ bool sample_q(const VolumeView &v, SlotCache &cache, 
 
 // First lattice index past the cell of block B along the ray (the caller's
 // samples before it all have their base voxel in B).
-__device__ __forceinline__ long long cell_exit_sample(const Ray &r, const int B[3], double h)
+// First lattice index past the cell of block B along the ray (the caller's
+// samples before it all have their base voxel in B).  The division by h is a
+// product with 1/h: the index found lies within one of the exit, and the
+// test of its sample then returns the exit or one index before it (a later
+// resume point is never returned).
+__device__ __forceinline__ int cell_exit_sample(const Ray &r, const int B[3], double h, double inv_h)
 {
     double s_exit = 1e300;
 #pragma unroll
@@ -250,7 +311,7 @@ __device__ __forceinline__ long long cell_exit_sample(const Ray &r, const int B[
         if (r.dq[a] > 0.0) s_exit = fmin(s_exit, (8.0 * (B[a] + 1) - r.q0[a]) * r.inv[a]);
         else if (r.dq[a] < 0.0) s_exit = fmin(s_exit, (8.0 * B[a] - r.q0[a]) * r.inv[a]);
     }
-    const long long m = (long long)floor(s_exit / h);
+    const int m = (int)fmin(floor(s_exit * inv_h), 2.0e9);
     double qm[3];
     q_at(r, (double)m * h, qm);
     const bool still = ((int)floor(qm[0]) >> 3) == B[0] && ((int)floor(qm[1]) >> 3) == B[1] &&
@@ -281,7 +342,7 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
     const double h = 0.5 * v.vs;
 
     Ray r;
-    long long n_lo = 1, n_end = 0;
+    int n_lo = 1, n_end = 0;   // sample indices (a ray crosses the grid in fewer than 2^31 samples)
     if (active) {
         const size_t t = (size_t)tj * tiles_x + ti;
         // the pixel's cell span joined with its tile's (blocks with large footprints)
@@ -319,51 +380,61 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
             s_out = fmin(s_out, (double)zmax_t * len);
         }
         if (!miss && s_in <= s_out) {
-            n_lo = max((long long)floor(s_in / h) - 1, 1ll);
-            n_end = (long long)ceil(s_out / h) + 1;
+            n_lo = max((int)fmin(floor(s_in / h) - 1.0, 2.0e9), 1);
+            n_end = (int)fmin(ceil(s_out / h) + 1.0, 2.0e9);
         }
     }
 
-    // ---- march: the group evaluates samples n_base .. n_base + G - 1 per step
+    // ---- march: the group evaluates samples n_base .. n_base + G - 1 per step.
+    // An invalid sample carries F = NaN, so every comparison with it fails.
+    const float kNaN = __builtin_nanf("");
     SlotCache cache;
     cache.B[0] = cache.B[1] = cache.B[2] = -(1 << 30);
-    long long n_base = n_lo;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cache.base[k] = v.capacity * (uint32_t)kBlockVoxels;   // the chi block
+    cache.empty = true;
+    cache.positive = false;
+    const double inv_h = 2.0 * v.inv_vs;
+    int n_base = n_lo;
     bool done = !(active && n_lo <= n_end);
     bool hit = false;
-    float Fc = 0.0f;     // carried last sample of the previous step (valid flag vc)
-    bool vc = false;
+    float Fc = kNaN;     // carried last sample of the previous step
     double s_lo = 0.0, s_hi = 0.0;
     float F_lo = 0.0f, F_hi = 0.0f;
     while (__ballot(!done)) {
-        const long long n = n_base + j;
-        bool valid = false, cell_empty = false, in_cell = false;
-        float F = 0.0f;
-        if (!done && n <= n_end) {
-            double q[3];
-            q_at(r, (double)n * h, q);
-            int c[3];
-            float f[3];
-            if (stencil(v, q, c, f)) {
-                if ((c[0] >> 3) != cache.B[0] || (c[1] >> 3) != cache.B[1] || (c[2] >> 3) != cache.B[2])
-                    fill_cache<kDense>(v, cache, c[0] >> 3, c[1] >> 3, c[2] >> 3);
-                in_cell = true;   // the cache now describes this sample's cell
-                cell_empty = cache.s[0] < 0;
-                if (!cell_empty) valid = interp_cached<S>(v, cache, c, f, F);
-            }
+        const int n = n_base + j;
+        // every lane evaluates its sample; the stencil of a lane outside the
+        // grid or past its ray's end reads valid pool memory and is discarded
+        double q[3];
+        q_at(r, (double)n * h, q);
+        int c[3];
+        float f[3];
+        const bool inside = stencil(v, q, c, f) && !done && n <= n_end;
+        const int b0 = c[0] >> 3, b1 = c[1] >> 3, b2 = c[2] >> 3;
+        const bool need = inside && (b0 != cache.B[0] || b1 != cache.B[1] || b2 != cache.B[2]);
+        if constexpr (kDense) {
+            refill_dense(v, cache, need, b0, b1, b2);
+        } else {
+            if (need) fill_cache<kDense>(v, cache, b0, b1, b2);
         }
+        float Fs;
+        const bool ok = interp_cached<S>(v, cache, c, f, Fs);
+        const float F = inside && !cache.empty && ok ? Fs : kNaN;
+        // the sample's cell: block coordinates and flags
+        const uint32_t info = inside ? ((uint32_t)b0 | ((uint32_t)b1 << 10) | ((uint32_t)b2 << 20) |
+                                        (cache.empty ? kInfoEmpty : (cache.positive ? kInfoPositive : 0u)))
+                                     : 0u;
         // pair every sample with its predecessor (lane j - 1, or the carry)
         const float Fp_sh = __shfl(F, group_lane<G>(lane, (j + G - 1) & (G - 1)));
-        const bool vp_sh = __shfl((int)valid, group_lane<G>(lane, (j + G - 1) & (G - 1))) != 0;
         const float Fp = j == 0 ? Fc : Fp_sh;
-        const bool vp = j == 0 ? vc : vp_sh;
-        const bool cross = !done && n <= n_end && valid && vp && Fp > 0.0f && F <= 0.0f;
+        const bool cross = !done && n <= n_end && Fp > 0.0f && F <= 0.0f;
         const unsigned long long m = __ballot(cross);
         const uint32_t gm = (uint32_t)(m >> (lane & ~(G - 1))) & ((G == 32 ? 0xffffffffu : (1u << G) - 1u));
         // (done and gm are the same in every lane of a group, so the group's
         // lanes all take part in these shuffles)
         if (!done && gm) {
             const int first = __builtin_ctz(gm);
-            const long long nh = n_base + first;
+            const int nh = n_base + first;
             s_lo = (double)(nh - 1) * h;
             s_hi = (double)nh * h;
             F_lo = __shfl(Fp, group_lane<G>(lane, first));
@@ -374,31 +445,26 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         // advance: the group's last lane decides a jump over its cell
         const int last = G - 1;
         const float F_last = __shfl(F, group_lane<G>(lane, last));
-        const bool v_last = __shfl((int)valid, group_lane<G>(lane, last)) != 0;
-        const bool empty_last = __shfl((int)(in_cell && cell_empty), group_lane<G>(lane, last)) != 0;
-        const bool pos_last = __shfl((int)(in_cell && !cell_empty && cache.positive), group_lane<G>(lane, last)) != 0;
-        const int B0 = __shfl(cache.B[0], group_lane<G>(lane, last));
-        const int B1 = __shfl(cache.B[1], group_lane<G>(lane, last));
-        const int B2 = __shfl(cache.B[2], group_lane<G>(lane, last));
+        const uint32_t info_last = (uint32_t)__shfl((int)info, group_lane<G>(lane, last));
         if (!done) {
-            const long long n_last = n_base + last;
-            long long next = n_last + 1;
+            const int n_last = n_base + last;
+            int next = n_last + 1;
             bool carry = true;
             if (n_last > n_end) {
                 done = true;
-            } else if (empty_last || pos_last) {
-                const int Bc[3] = {B0, B1, B2};
-                const long long exit_n = cell_exit_sample(r, Bc, h);   // first sample past the cell
+            } else if (info_last & (kInfoEmpty | kInfoPositive)) {
+                const int Bc[3] = {(int)(info_last & 1023u), (int)((info_last >> 10) & 1023u),
+                                   (int)((info_last >> 20) & 1023u)};
+                const int exit_n = cell_exit_sample(r, Bc, h, inv_h);   // first sample past the cell
                 // empty: every sample before the exit is invalid; positive: none
                 // before the cell's last sample can end a crossing
-                const long long target = empty_last ? exit_n : exit_n - 1;
+                const int target = (info_last & kInfoEmpty) ? exit_n : exit_n - 1;
                 if (target > next) {
                     next = target;
                     carry = false;
                 }
             }
-            Fc = carry ? F_last : 0.0f;
-            vc = carry && v_last;
+            Fc = carry ? F_last : kNaN;
             n_base = next;
             if (n_base > n_end) done = true;
         }
@@ -415,30 +481,27 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
     for (int it = 0; it < kSteps; ++it) {
         if (!__ballot(refine)) break;
         float Fp[kPts];
-        bool vp[kPts];
 #pragma unroll
         for (int rd = 0; rd < kRounds; ++rd) {
             const int m = rd * G + j;
-            float Fm = 0.0f;
-            bool vm = false;
+            float Fm = kNaN;
             if (refine && m < kPts) {
                 double qm[3];
                 q_at(r, a + (b - a) * (double)(m + 1) * 0.25, qm);
-                vm = sample_q<S, kDense>(v, cache, qm, Fm);
+                float Fs;
+                if (sample_q<S, kDense>(v, cache, qm, Fs)) Fm = Fs;
             }
 #pragma unroll
-            for (int mm = rd * G; mm < (rd + 1) * G && mm < kPts; ++mm) {
+            for (int mm = rd * G; mm < (rd + 1) * G && mm < kPts; ++mm)
                 Fp[mm] = __shfl(Fm, group_lane<G>(lane, mm - rd * G));
-                vp[mm] = __shfl((int)vm, group_lane<G>(lane, mm - rd * G)) != 0;
-            }
         }
         if (refine) {
             bool bad = false;
             int k = kPts;   // first non-positive point: the root lies in (point k-1, point k]
 #pragma unroll
             for (int mm = kPts - 1; mm >= 0; --mm) {
-                bad |= !vp[mm];
-                if (vp[mm] && Fp[mm] <= 0.0f) k = mm;
+                bad |= Fp[mm] != Fp[mm];   // NaN: invalid
+                if (Fp[mm] <= 0.0f) k = mm;
             }
             if (bad) {
                 refine = false;   // an invalid point inside the bracket: keep the bracket
@@ -467,27 +530,22 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         double qh[3];
         q_at(r, sh, qh);
         float Fs[6];
-        bool vs[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            Fs[e] = 0.0f;
-            vs[e] = false;
-        }
+        for (int e = 0; e < 6; ++e) Fs[e] = kNaN;
         // sample e in {+x, -x, +y, -y, +z, -z} is taken by lane e % G of the group
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             if (hit && (e % G) == j) {
                 double qe[3] = {qh[0], qh[1], qh[2]};
                 qe[e >> 1] += (e & 1) ? -1.0 : 1.0;
-                vs[e] = sample_q<S, kDense>(v, cache, qe, Fs[e]);
+                float Fv;
+                if (sample_q<S, kDense>(v, cache, qe, Fv)) Fs[e] = Fv;
             }
         }
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-            const int src = group_lane<G>(lane, e % G);
-            Fs[e] = __shfl(Fs[e], src);
-            vs[e] = __shfl((int)vs[e], src) != 0;
-            ok = ok && vs[e];
+            Fs[e] = __shfl(Fs[e], group_lane<G>(lane, e % G));
+            ok = ok && Fs[e] == Fs[e];   // NaN: invalid
         }
         g[0] = Fs[0] - Fs[1];
         g[1] = Fs[2] - Fs[3];

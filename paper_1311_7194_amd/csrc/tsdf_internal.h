@@ -32,7 +32,7 @@ static_assert(sizeof(DeviceState) == 256, "state line");
 // Event counters, spread over kCtrLanes addresses so that thousands of
 // wavefronts do not serialise on one atomic; the host sums the lanes.
 // Edge in pixels of the cells of the raycast's per-cell depth spans.
-constexpr int kCell = 2;
+constexpr int kCell = 4;
 
 constexpr int kCtrLanes = 256;
 enum { CTR_UPDATES = 0, CTR_FRESH = 1, CTR_NEW = 2, CTR_TOUCHED = 3, CTR_N = 4 };
@@ -106,7 +106,8 @@ __host__ __device__ inline uint32_t hash_key(uint32_t k)
 }
 __host__ __device__ inline uint64_t block_linear(const VolumeView &v, int bx, int by, int bz)
 {
-    return ((uint64_t)bz * (uint64_t)v.nblk[1] + (uint64_t)by) * (uint64_t)v.nblk[0] + (uint64_t)bx;
+    // at most 1024 blocks per axis: the index fits in 30 bits
+    return (uint64_t)(((uint32_t)bz * (uint32_t)v.nblk[1] + (uint32_t)by) * (uint32_t)v.nblk[0] + (uint32_t)bx);
 }
 
 // Lookup: slot or -1.
@@ -145,6 +146,8 @@ __device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
     return -1;
 }
 
+// Largest pool: slot * 512 + voxel stays below 2^31 (32-bit pool offsets).
+constexpr uint32_t kMaxCapacity = 1u << 22;
 constexpr int32_t kIndexPositive = 1 << 30;   // dense index: every non-chi value of the block is > 0
 constexpr int32_t kIndexSlotMask = kIndexPositive - 1;
 
@@ -186,8 +189,9 @@ hipError_t launch_frame_begin(const VolumeView &v, hipStream_t s);
 hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &cam, const NoiseParams &noise,
                        hipStream_t s);
 hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s);
-hipError_t launch_raycast(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
-                          float4 *normal, hipStream_t s);
+hipError_t launch_range(const VolumeView &v, const Camera &cam, uint32_t stamp, hipStream_t s);
+hipError_t launch_march(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
+                        float4 *normal, hipStream_t s);
 hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
 hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,
                          hipStream_t s);

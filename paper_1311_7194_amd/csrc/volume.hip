@@ -131,7 +131,7 @@ static bool valid_desc(const tsdf_volume_desc *d)
     for (int a = 0; a < 3; ++a)
         if (!isfinite(d->origin[a])) return false;
     if (!(d->trunc_voxels > 0) || !isfinite(d->trunc_voxels)) return false;
-    if (d->capacity_blocks == 0 || d->capacity_blocks > (1u << 30)) return false;
+    if (d->capacity_blocks == 0 || d->capacity_blocks > kMaxCapacity) return false;
     if (d->hash_slots == 0 || (d->hash_slots & (d->hash_slots - 1)) != 0) return false;
     if ((uint64_t)d->hash_slots < 2ull * d->capacity_blocks) return false;
     if (d->storage != TSDF_F32 && d->storage != TSDF_F16) return false;
@@ -177,10 +177,11 @@ static Layout layout_of(const tsdf_volume_desc *d)
     L.pix_range = off;
     off = align256(off + 8ull * (uint64_t)((d->max_width + kCell - 1) / kCell) *
                              (uint64_t)((d->max_height + kCell - 1) / kCell));
+    // one block past the capacity: the chi block that absent neighbours read
     L.poolT = off;
-    off = align256(off + elem * kBlockVoxels * (uint64_t)d->capacity_blocks);
+    off = align256(off + elem * kBlockVoxels * ((uint64_t)d->capacity_blocks + 1));
     L.poolP = off;
-    off = align256(off + elem * kBlockVoxels * (uint64_t)d->capacity_blocks);
+    off = align256(off + elem * kBlockVoxels * ((uint64_t)d->capacity_blocks + 1));
     L.total = off;
     return L;
 }
@@ -189,7 +190,7 @@ static Layout layout_of(const tsdf_volume_desc *d)
 
 using namespace tsdf;
 
-enum { STAGE_PREP = 0, STAGE_FUSE = 1, STAGE_RAYCAST = 2, N_STAGES = 3 };
+enum { STAGE_PREP = 0, STAGE_FUSE = 1, STAGE_RANGE = 2, STAGE_RAYCAST = 3, N_STAGES = 4 };
 
 struct EventPair {
     int stage;
@@ -325,6 +326,12 @@ static tsdf_status clear_volume(tsdf_volume *v, hipStream_t s)
     if (e == hipSuccess && v->desc.dense_index)
         e = fill_u32((uint32_t *)(v->base + L.block_index), L.nblocks, 0xffffffffu, s);
     if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.cand_bits), L.bitmap_words, 0u, s);
+    // the chi block (T = 2 in either storage type, P = 0)
+    const uint64_t elem = v->desc.storage == TSDF_F16 ? 2 : 4;
+    const uint64_t chi_off = elem * kBlockVoxels * (uint64_t)v->desc.capacity_blocks;
+    const uint32_t chi_word = v->desc.storage == TSDF_F16 ? 0x40004000u : 0x40000000u;
+    if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.poolT + chi_off), elem * kBlockVoxels / 4, chi_word, s);
+    if (e == hipSuccess) e = fill_u32((uint32_t *)(v->base + L.poolP + chi_off), elem * kBlockVoxels / 4, 0u, s);
     v->host_flags = 0;
     v->last_stream = s;
     return hip_status(e);
@@ -463,9 +470,12 @@ tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const doubl
     vol->last_stream = stream;
     const VolumeView &w = vol->view;
     const uint32_t stamp = ++vol->raycast_stamp == 0 ? ++vol->raycast_stamp : vol->raycast_stamp;
-    return hip_status(timed(vol, STAGE_RAYCAST, stream, [&] {
-        return launch_raycast(w, cam, stamp, vol->ray_group, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
-    }));
+    hipError_t e = timed(vol, STAGE_RANGE, stream, [&] { return launch_range(w, cam, stamp, stream); });
+    if (e == hipSuccess)
+        e = timed(vol, STAGE_RAYCAST, stream, [&] {
+            return launch_march(w, cam, stamp, vol->ray_group, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
+        });
+    return hip_status(e);
 }
 
 tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out)
@@ -568,9 +578,11 @@ tsdf_status tsdf_read_timing(tsdf_volume *vol, tsdf_timing *out, int32_t reset)
     hipError_t e = collect_timing(vol);
     out->prep_ms = vol->stage_ms[STAGE_PREP];
     out->fuse_ms = vol->stage_ms[STAGE_FUSE];
+    out->range_ms = vol->stage_ms[STAGE_RANGE];
     out->raycast_ms = vol->stage_ms[STAGE_RAYCAST];
     out->prep_launches = vol->stage_launches[STAGE_PREP];
     out->fuse_launches = vol->stage_launches[STAGE_FUSE];
+    out->range_launches = vol->stage_launches[STAGE_RANGE];
     out->raycast_launches = vol->stage_launches[STAGE_RAYCAST];
     if (reset)
         for (int k = 0; k < N_STAGES; ++k) {

@@ -210,3 +210,25 @@ def run(size: ExperimentSize, seed: int = 0, log=print) -> dict:
                 surface_diff_vox=paired("surface_quadratic_vox", "surface_learned_vox"),
                 tsdf_rms_diff_vox=paired("tsdf_rms_quadratic_vox", "tsdf_rms_learned_vox"),
                 params=trainer.params, wall_s=time.time() - t0)
+
+
+def main():
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description="learned measurement-noise experiment (one GPU)")
+    ap.add_argument("--size", choices=["small", "full"], default="small")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--train", type=int, default=0, help="use only the first N training sequences (0: all)")
+    a = ap.parse_args()
+    size = full_size() if a.size == "full" else small_size()
+    if a.train:
+        size.train_seeds = size.train_seeds[:a.train]
+    res = run(size, a.seed, log=lambda m: print(m, file=sys.stderr, flush=True))
+    res.pop("params")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,8 +66,9 @@ class Stats(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("prep_ms", ctypes.c_double), ("fuse_ms", ctypes.c_double), ("raycast_ms", ctypes.c_double),
-                ("prep_launches", ctypes.c_uint64), ("fuse_launches", ctypes.c_uint64),
+    _fields_ = [("prep_ms", ctypes.c_double), ("fuse_ms", ctypes.c_double), ("range_ms", ctypes.c_double),
+                ("raycast_ms", ctypes.c_double), ("prep_launches", ctypes.c_uint64),
+                ("fuse_launches", ctypes.c_uint64), ("range_launches", ctypes.c_uint64),
                 ("raycast_launches", ctypes.c_uint64)]
 
     def as_dict(self):

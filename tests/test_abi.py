@@ -61,8 +61,8 @@ def test_volume_bytes_accounts_for_pool_and_index(lib):
     assert rc == T.OK
     rc, b16 = nbytes(lib, desc(storage=1))
     assert rc == T.OK
-    # pool: 2 arrays x capacity x 512 voxels x element size
-    assert b32 - b16 == 2 * (1 << 14) * 512 * 2
+    # pool: 2 arrays x (capacity + the chi block) x 512 voxels x element size
+    assert b32 - b16 == 2 * ((1 << 14) + 1) * 512 * 2
     assert b32 >= 2 * (1 << 14) * 512 * 4 + 8 * (1 << 15)
 
 
@@ -73,6 +73,7 @@ def test_volume_bytes_accounts_for_pool_and_index(lib):
     dict(voxel_size=float("nan")),
     dict(trunc_voxels=-1.0),
     dict(capacity_blocks=0),
+    dict(capacity_blocks=(1 << 22) + 1, hash_slots=1 << 24),   # beyond 32-bit pool offsets
     dict(hash_slots=3 << 14),            # not a power of two
     dict(hash_slots=1 << 14),            # below twice the capacity
     dict(storage=7),
