@@ -92,7 +92,8 @@ __device__ __forceinline__ int scene_at(const uint32_t *pre, int n, uint32_t g)
 // Persistent fusion over the concatenation of every active scene's candidates;
 // a wavefront's counts go to a scene's counters when it moves on to the next.
 template <typename S>
-__global__ __launch_bounds__(256) void batch_fuse(const SceneDesc *__restrict__ sd, int n)
+// five waves per SIMD: a few spilled registers cost less than the lost latency hiding
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void batch_fuse(const SceneDesc *__restrict__ sd, int n)
 {
     __shared__ uint32_t pre[kMaxScenes + 1];
     scene_prefix<false>(sd, n, pre);

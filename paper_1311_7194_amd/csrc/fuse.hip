@@ -48,7 +48,8 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void fuse_kernel(VolumeView v, Camera cam, FuseCam fc)
+// five waves per SIMD: a few spilled registers cost less than the lost latency hiding
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void fuse_kernel(VolumeView v, Camera cam, FuseCam fc)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);

@@ -403,8 +403,6 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
     float F_lo = 0.0f, F_hi = 0.0f;
     while (__ballot(!done)) {
         const int n = n_base + j;
-        // every lane evaluates its sample; the stencil of a lane outside the
-        // grid or past its ray's end reads valid pool memory and is discarded
         double q[3];
         q_at(r, (double)n * h, q);
         int c[3];
@@ -417,10 +415,11 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         } else {
             if (need) fill_cache<kDense>(v, cache, b0, b1, b2);
         }
-        float Fs;
-        const bool ok = interp_cached<S>(v, cache, c, f, Fs);
-        const float F = inside && !cache.empty && ok ? Fs : kNaN;
-        // the sample's cell: block coordinates and flags
+        float F = kNaN;
+        if (inside && !cache.empty) {
+            float Fs;
+            if (interp_cached<S>(v, cache, c, f, Fs)) F = Fs;
+        }
         const uint32_t info = inside ? ((uint32_t)b0 | ((uint32_t)b1 << 10) | ((uint32_t)b2 << 20) |
                                         (cache.empty ? kInfoEmpty : (cache.positive ? kInfoPositive : 0u)))
                                      : 0u;
