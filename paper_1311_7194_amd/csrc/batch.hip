@@ -132,12 +132,35 @@ __global__ void batch_range_clear(const SceneDesc *__restrict__ sd, int n, uint3
 __global__ __launch_bounds__(256) void batch_range(const SceneDesc *__restrict__ sd, int n)
 {
     __shared__ uint32_t pre[kMaxScenes + 1];
-    scene_prefix<true>(sd, n, pre);
+    __shared__ SpanLds L;
+    span_lds_init(L);
+    scene_prefix<true>(sd, n, pre);   // (synchronises the workgroup)
     for (uint32_t g = blockIdx.x * 256u + threadIdx.x; g < pre[n]; g += gridDim.x * 256u) {
         int s = 0;
         for (int k = 1; k < n; ++k) s += pre[k] <= g ? 1 : 0;
         const SceneDesc &d = sd[s];
-        range_block(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, g - pre[s]);
+        range_block(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, g - pre[s],
+                    [&](uint32_t c, uint32_t zl, uint32_t zh) {
+                        if (!span_lds_add(L, ((uint32_t)s << 26) | c, zl, zh)) {
+                            uint32_t *cmin = d.v.pix_range;
+                            uint32_t *cmax = cmin + (size_t)((d.cam.width + kCell - 1) / kCell) *
+                                                        ((d.cam.height + kCell - 1) / kCell);
+                            atomicMin(&cmin[c], zl);
+                            atomicMax(&cmax[c], zh);
+                        }
+                    });
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kSpanLds; e += 256) {
+        const uint32_t key = L.key[e];
+        if (key != kSpanEmpty) {
+            const SceneDesc &d = sd[key >> 26];
+            const uint32_t c = key & ((1u << 26) - 1u);
+            uint32_t *cmin = d.v.pix_range;
+            uint32_t *cmax = cmin + (size_t)((d.cam.width + kCell - 1) / kCell) * ((d.cam.height + kCell - 1) / kCell);
+            atomicMin(&cmin[c], L.lo[e]);
+            atomicMax(&cmax[c], L.hi[e]);
+        }
     }
 }
 

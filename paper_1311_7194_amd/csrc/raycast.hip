@@ -39,9 +39,27 @@ __global__ void range_clear_kernel(VolumeView v, int tiles_x, int tiles_y, int w
 __global__ __launch_bounds__(256) void range_kernel(VolumeView v, Camera cam, uint32_t stamp, int tiles_x,
                                                     int tiles_y)
 {
+    __shared__ SpanLds L;
+    span_lds_init(L);
+    __syncthreads();
+    const int cw = (cam.width + kCell - 1) / kCell, ch = (cam.height + kCell - 1) / kCell;
+    uint32_t *cmin = v.pix_range, *cmax = v.pix_range + (size_t)cw * ch;
     const uint32_t n = min(v.state->pool_count, v.capacity);
     for (uint32_t slot = blockIdx.x * 256u + threadIdx.x; slot < n; slot += gridDim.x * 256u)
-        range_block(v, cam, stamp, tiles_x, tiles_y, slot);
+        range_block(v, cam, stamp, tiles_x, tiles_y, slot, [&](uint32_t c, uint32_t zl, uint32_t zh) {
+            if (!span_lds_add(L, c, zl, zh)) {
+                atomicMin(&cmin[c], zl);   // no return value: the lane does not wait
+                atomicMax(&cmax[c], zh);
+            }
+        });
+    __syncthreads();
+    for (int e = threadIdx.x; e < kSpanLds; e += 256) {
+        const uint32_t c = L.key[e];
+        if (c != kSpanEmpty) {
+            atomicMin(&cmin[c], L.lo[e]);
+            atomicMax(&cmax[c], L.hi[e]);
+        }
+    }
 }
 
 template <typename S, int G, bool kDense>

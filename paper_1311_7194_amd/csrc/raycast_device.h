@@ -44,9 +44,47 @@ __device__ __forceinline__ void range_clear_body(const VolumeView &v, int tiles_
 
 // ------------------------------------------------------------ range pass
 
-// One allocated block (pool slot) of the range pass.
+// Cell spans gathered in LDS by one workgroup before they go to memory:
+// consecutive pool slots are neighbours in space, so their blocks widen the
+// same cells, and one pair of memory atomics per distinct cell replaces one
+// per block.  Keys are (scene << 26) | cell.
+constexpr int kSpanLds = 2048;
+constexpr uint32_t kSpanEmpty = 0xffffffffu;
+struct SpanLds {
+    uint32_t key[kSpanLds], lo[kSpanLds], hi[kSpanLds];
+};
+
+__device__ __forceinline__ void span_lds_init(SpanLds &L)
+{
+    for (int e = threadIdx.x; e < kSpanLds; e += blockDim.x) {
+        L.key[e] = kSpanEmpty;
+        L.lo[e] = kInfBits;
+        L.hi[e] = 0u;
+    }
+}
+
+// Widens the entry of `key` (false when its probe run is full).
+__device__ __forceinline__ bool span_lds_add(SpanLds &L, uint32_t key, uint32_t zl, uint32_t zh)
+{
+    uint32_t h = (key * 2654435761u) >> (32 - 11);
+#pragma unroll 1
+    for (int p = 0; p < 8; ++p) {
+        const uint32_t k = atomicCAS(&L.key[h], kSpanEmpty, key);
+        if (k == kSpanEmpty || k == key) {
+            atomicMin(&L.lo[h], zl);
+            atomicMax(&L.hi[h], zh);
+            return true;
+        }
+        h = (h + 1) & (kSpanLds - 1);
+    }
+    return false;
+}
+
+// One allocated block (pool slot) of the range pass.  Cell spans go to
+// `emit(cell, zl, zh)`; tile spans and the near-plane stamp go to memory.
+template <typename Emit>
 __device__ __forceinline__ void range_block(const VolumeView &v, const Camera &cam, uint32_t stamp, int tiles_x,
-                                            int tiles_y, uint32_t slot)
+                                            int tiles_y, uint32_t slot, Emit &&emit)
 {
     uint32_t *tmin = v.tile_range;
     uint32_t *tmax = v.tile_range + (size_t)tiles_x * tiles_y;
@@ -100,14 +138,9 @@ __device__ __forceinline__ void range_block(const VolumeView &v, const Camera &c
     const int c0 = i0 / kCell, c1 = i1 / kCell, d0 = j0 / kCell, d1 = j1 / kCell;
     if ((c1 - c0 + 1) * (d1 - d0 + 1) <= kCellFootprint) {
         // small footprint: widen the span of every cell it covers
-        const int cw = (cam.width + kCell - 1) / kCell, ch = (cam.height + kCell - 1) / kCell;
-        uint32_t *cmin = v.pix_range, *cmax = v.pix_range + (size_t)cw * ch;
+        const int cw = (cam.width + kCell - 1) / kCell;
         for (int d = d0; d <= d1; ++d)
-            for (int c = c0; c <= c1; ++c) {
-                const size_t p = (size_t)d * cw + c;
-                atomicMin(&cmin[p], zl);   // no return value: the lane does not wait
-                atomicMax(&cmax[p], zh);
-            }
+            for (int c = c0; c <= c1; ++c) emit((uint32_t)(d * cw + c), zl, zh);
         return;
     }
     // large footprint (blocks close to the camera): widen whole tiles
