@@ -139,6 +139,33 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
     return res
 
 
+def raycast_footprint(res, spec, storage, steps, noise=None):
+    """Replays the timed sequence outside the timed region with the
+    instrumented raycast and returns the mean number of blocks whose voxels a
+    frame's march reads; with the output and the span maps this gives the
+    raycast's algorithmic bytes per launch."""
+    vol = res["_vol"]
+    depths, poses = res["_frames"]
+    K = spec.K
+    kind = 0 if noise is None else 2
+    vol.reset()
+    vert = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(vert)
+    total = 0
+    for k in range(steps):
+        vol.integrate(depths[k], K, poses[k], kind, 0.0015, noise)
+        n, _, _ = vol.raycast_footprint(K, poses[k], vert, nrm)
+        total += n
+    elem = 2 if storage == 1 else 4
+    blocks = total / steps
+    cells = ((K.width + 3) // 4) * ((K.height + 3) // 4)
+    tiles = ((K.width + 7) // 8) * ((K.height + 7) // 8)
+    res["raycast_blocks_read"] = blocks
+    res["raycast_bytes"] = 32 * K.width * K.height + 512 * elem * blocks + 8 * (cells + tiles)
+    res["raycast_gbs"] = res["raycast_bytes"] / (res["raycast_avg_us"] * 1e-6) / 1e9
+    return res
+
+
 KERNEL_SOURCES = ("fuse_device.h", "fuse.hip", "raycast_device.h", "raycast.hip", "tsdf_internal.h",
                   "mlp_device.h", "mlp_features.h", "volume.hip")
 
@@ -185,11 +212,16 @@ def roofline_of(res):
         return dict(kernel="fuse_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=t,
                     bytes_per_launch=int(per_launch), avg_launch_us=round(res["fuse_avg_us"], 2))
-    achieved = res["raycast_gbs_output_only"]
+    # algorithmic bytes: the maps written, the voxel blocks the march reads
+    # (counted by the instrumented replay) and the span maps; without the
+    # replay, the maps alone (a lower bound)
+    per_launch = res.get("raycast_bytes", 32 * res["width"] * res["height"])
+    achieved = per_launch / (res["raycast_avg_us"] * 1e-6) / 1e9
     t = profiled_traffic("raycast_kernel", f"{res['workload']}/{res['storage']}")
     return dict(kernel="raycast_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5), traffic=t,
-                bytes_per_launch=32 * res["width"] * res["height"], avg_launch_us=round(res["raycast_avg_us"], 2))
+                bytes_per_launch=int(per_launch), avg_launch_us=round(res["raycast_avg_us"], 2),
+                blocks_read_per_launch=round(res.get("raycast_blocks_read", 0.0), 1))
 
 
 def run_batch_c5(steps=None, warmup=3, reps_tune=3):
@@ -367,6 +399,7 @@ def main():
     storage = 1 if args.storage == "f16" else 0
     spec = make_spec(args.config, args.steps)
     res = run_sequence(spec, storage, args.steps, args.warmup)
+    raycast_footprint(res, spec, storage, args.steps)
     log(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}))
     out = {
         "metric": METRIC,
@@ -408,7 +441,9 @@ def main():
     if args.variants and args.config != "c3":
         spec3 = make_spec("c3", args.variant_steps)
         r32 = run_sequence(spec3, 0, args.variant_steps, 3)
+        raycast_footprint(r32, spec3, 0, args.variant_steps)
         r16 = run_sequence(spec3, 1, args.variant_steps, 3)
+        raycast_footprint(r16, spec3, 1, args.variant_steps)
         cmp = compare_storage(r16["_vol"], r32["_vol"])
         for r in (r32, r16):
             variants.append({"workload": r["workload"], "storage": r["storage"], "frames": r["frames"],

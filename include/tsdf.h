@@ -157,6 +157,16 @@ tsdf_status tsdf_integrate_frame(tsdf_volume *vol, const float *depth_dev, const
 tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
                          float *vertex_dev, float *normal_dev, hipStream_t stream);
 
+/* The raycast above, also counting the blocks whose voxels the rays' march
+ * samples are based in (each block once, however many rays read it).  This
+ * is the data the raycast must read from the pool: the measure of its
+ * algorithmic traffic.  The maps are bitwise those of tsdf_raycast.  Runs an
+ * instrumented copy of the march (not the one tsdf_raycast times) and
+ * synchronises `stream` to return *blocks_out. */
+tsdf_status tsdf_raycast_footprint(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
+                                   float *vertex_dev, float *normal_dev, uint64_t *blocks_out,
+                                   hipStream_t stream);
+
 /* Lanes that march one ray together in the raycast (1, 2, 4, 8 or 16; default 8).
  * Every group size gives bitwise the same maps; only the speed differs. */
 tsdf_status tsdf_set_raycast_group(tsdf_volume *vol, int32_t group);

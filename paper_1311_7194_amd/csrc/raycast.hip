@@ -62,26 +62,34 @@ __global__ __launch_bounds__(256) void range_kernel(VolumeView v, Camera cam, ui
     }
 }
 
-template <typename S, int G, bool kDense>
+template <typename S, int G, bool kDense, bool kMark = false>
 __global__ __launch_bounds__(256) void raycast_kernel(VolumeView v, Camera cam, uint32_t stamp, int tiles_x,
                                                       int tiles_y, float4 *__restrict__ vertex,
                                                       float4 *__restrict__ normal)
 {
-    raycast_body<S, G, kDense>(v, cam, stamp, tiles_x, tiles_y, vertex, normal,
+    raycast_body<S, G, kDense, kMark>(v, cam, stamp, tiles_x, tiles_y, vertex, normal,
                                (long long)blockIdx.x * 256 + threadIdx.x);
 }
 
-template <typename S, bool kDense>
+template <typename S, bool kDense, bool kMark>
 static void launch_group(int G, dim3 grid, hipStream_t s, const VolumeView &v, const Camera &cam, uint32_t stamp,
                          int tx, int ty, float4 *vertex, float4 *normal)
 {
     switch (G) {
-    case 1: hipLaunchKernelGGL((raycast_kernel<S, 1, kDense>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
-    case 2: hipLaunchKernelGGL((raycast_kernel<S, 2, kDense>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
-    case 4: hipLaunchKernelGGL((raycast_kernel<S, 4, kDense>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
-    case 16: hipLaunchKernelGGL((raycast_kernel<S, 16, kDense>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
-    default: hipLaunchKernelGGL((raycast_kernel<S, 8, kDense>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
+    case 1: hipLaunchKernelGGL((raycast_kernel<S, 1, kDense, kMark>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
+    case 2: hipLaunchKernelGGL((raycast_kernel<S, 2, kDense, kMark>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
+    case 4: hipLaunchKernelGGL((raycast_kernel<S, 4, kDense, kMark>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
+    case 16: hipLaunchKernelGGL((raycast_kernel<S, 16, kDense, kMark>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
+    default: hipLaunchKernelGGL((raycast_kernel<S, 8, kDense, kMark>), grid, dim3(256), 0, s, v, cam, stamp, tx, ty, vertex, normal); break;
     }
+}
+
+template <typename S, bool kDense>
+static void launch_group(bool mark, int G, dim3 grid, hipStream_t s, const VolumeView &v, const Camera &cam,
+                         uint32_t stamp, int tx, int ty, float4 *vertex, float4 *normal)
+{
+    if (mark) launch_group<S, kDense, true>(G, grid, s, v, cam, stamp, tx, ty, vertex, normal);
+    else launch_group<S, kDense, false>(G, grid, s, v, cam, stamp, tx, ty, vertex, normal);
 }
 
 hipError_t launch_range(const VolumeView &v, const Camera &cam, uint32_t stamp, hipStream_t s)
@@ -96,7 +104,7 @@ hipError_t launch_range(const VolumeView &v, const Camera &cam, uint32_t stamp, 
 }
 
 hipError_t launch_march(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
-                        float4 *normal, hipStream_t s)
+                        float4 *normal, hipStream_t s, bool mark)
 {
     const int tiles_x = (cam.width + kRT - 1) / kRT, tiles_y = (cam.height + kRT - 1) / kRT;
     const int G = (group == 1 || group == 2 || group == 4 || group == 16) ? group : 8;
@@ -104,12 +112,30 @@ hipError_t launch_march(const VolumeView &v, const Camera &cam, uint32_t stamp, 
     dim3 grid((unsigned)((threads + 255) / 256));
     const bool dense = v.block_index != nullptr;
     if (v.storage == TSDF_F16) {
-        if (dense) launch_group<__half, true>(G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
-        else launch_group<__half, false>(G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
+        if (dense) launch_group<__half, true>(mark, G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
+        else launch_group<__half, false>(mark, G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
     } else {
-        if (dense) launch_group<float, true>(G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
-        else launch_group<float, false>(G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
+        if (dense) launch_group<float, true>(mark, G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
+        else launch_group<float, false>(mark, G, grid, s, v, cam, stamp, tiles_x, tiles_y, vertex, normal);
     }
+    return hipGetLastError();
+}
+
+// Number of set bits of a bitmap, added to the device state's footprint field.
+__global__ __launch_bounds__(256) void count_bits_kernel(const uint32_t *__restrict__ bits, uint64_t words,
+                                                         unsigned long long *__restrict__ out)
+{
+    unsigned long long c = 0;
+    for (uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x; w < words; w += (uint64_t)gridDim.x * 256)
+        c += (unsigned long long)__popc(bits[w]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+hipError_t launch_count_bits(const uint32_t *bits, uint64_t words, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_bits_kernel, dim3(1024), dim3(256), 0, s, bits, words, out);
     return hipGetLastError();
 }
 

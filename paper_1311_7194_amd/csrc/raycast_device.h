@@ -357,7 +357,9 @@ template <int G>
 __device__ __forceinline__ int group_lane(int lane, int src) { return (lane & ~(G - 1)) | src; }
 
 // Thread `gt` of a launch space of (tiles x 64 rays x G lanes) for one frame.
-template <typename S, int G, bool kDense>
+// kMark: also set the bit of every block a march sample is based in (the
+// footprint query; the timed raycast is instantiated without it).
+template <typename S, int G, bool kDense, bool kMark = false>
 __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &cam, uint32_t stamp, int tiles_x,
                                              int tiles_y, float4 *__restrict__ vertex, float4 *__restrict__ normal,
                                              long long gt)
@@ -447,6 +449,12 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
             refill_dense(v, cache, need, b0, b1, b2);
         } else {
             if (need) fill_cache<kDense>(v, cache, b0, b1, b2);
+        }
+        if constexpr (kMark) {
+            if (need && !cache.empty) {
+                const uint64_t lb = block_linear(v, b0, b1, b2);
+                atomicOr(&v.mark_bits[lb >> 5], 1u << (lb & 31));
+            }
         }
         float F = kNaN;
         if (inside && !cache.empty) {

@@ -25,7 +25,8 @@ struct DeviceState {
     uint32_t near_stamp;     // raycast call id whose range pass met a block at the camera plane
     unsigned long long frames;
     unsigned long long total_candidates;
-    uint32_t pad[56];
+    unsigned long long footprint;   // blocks counted by the last raycast footprint query
+    uint32_t pad[54];
 };
 static_assert(sizeof(DeviceState) == 256, "state line");
 
@@ -50,6 +51,7 @@ struct VolumeView {
     uint32_t *block_min;        // capacity entries: ordered key of a lower bound of the block's non-chi T
     uint32_t *tile_range;       // raycast: per 8x8 pixel tile (min depth bits, max depth bits)
     uint32_t *pix_range;        // raycast: per kCell x kCell pixel cell (min depth bits, max depth bits)
+    uint32_t *mark_bits;        // one bit per virtual block: blocks a footprint query's rays read
     uint32_t *occupancy;        // one bit per block of the virtual grid
     int32_t *block_index;       // optional dense index per virtual block: slot | positive << 30, -1 = empty
     uint32_t *cand_bits;        // per-frame candidate dedup bits (all clear between frames)
@@ -190,8 +192,9 @@ hipError_t launch_prep(const VolumeView &v, const float *depth, const Camera &ca
                        hipStream_t s);
 hipError_t launch_fuse(const VolumeView &v, const Camera &cam, hipStream_t s);
 hipError_t launch_range(const VolumeView &v, const Camera &cam, uint32_t stamp, hipStream_t s);
+hipError_t launch_count_bits(const uint32_t *bits, uint64_t words, unsigned long long *out, hipStream_t s);
 hipError_t launch_march(const VolumeView &v, const Camera &cam, uint32_t stamp, int group, float4 *vertex,
-                        float4 *normal, hipStream_t s);
+                        float4 *normal, hipStream_t s, bool mark = false);
 hipError_t launch_export(const VolumeView &v, int32_t *keys, void *T, void *P, uint32_t cap, hipStream_t s);
 hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T, const void *P, uint32_t n,
                          hipStream_t s);

@@ -115,7 +115,7 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // ------------------------------------------------------------ layout
 
 struct Layout {
-    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range, pix_range,
+    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range, pix_range, mark_bits,
         poolT, poolP, total;
     uint64_t bitmap_words, tile_words, nblocks;
 };
@@ -162,6 +162,8 @@ static Layout layout_of(const tsdf_volume_desc *d)
     L.block_index = off;
     if (d->dense_index) off = align256(off + 4ull * nblocks);
     L.cand_bits = off;
+    off = align256(off + 4ull * L.bitmap_words);
+    L.mark_bits = off;
     off = align256(off + 4ull * L.bitmap_words);
     L.cand_list = off;
     off = align256(off + 4ull * maxc);
@@ -385,6 +387,7 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     w.block_min = (uint32_t *)(v->base + L.block_min);
     w.tile_range = (uint32_t *)(v->base + L.tile_range);
     w.pix_range = (uint32_t *)(v->base + L.pix_range);
+    w.mark_bits = (uint32_t *)(v->base + L.mark_bits);
     w.max_width = desc->max_width;
     w.max_height = desc->max_height;
     v->raycast_stamp = 0;
@@ -476,6 +479,31 @@ tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const doubl
             return launch_march(w, cam, stamp, vol->ray_group, (float4 *)vertex_dev, (float4 *)normal_dev, stream);
         });
     return hip_status(e);
+}
+
+tsdf_status tsdf_raycast_footprint(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
+                                   float *vertex_dev, float *normal_dev, uint64_t *blocks_out, hipStream_t stream)
+{
+    if (!vol || !valid_intrinsics(K) || !valid_pose(pose_c2w) || !vertex_dev || !normal_dev || !blocks_out)
+        return TSDF_EINVAL;
+    if (K->width > vol->desc.max_width || K->height > vol->desc.max_height) return TSDF_EINVAL;
+    Camera cam = make_camera(K, pose_c2w);
+    vol->last_stream = stream;
+    const VolumeView &w = vol->view;
+    const uint32_t stamp = ++vol->raycast_stamp == 0 ? ++vol->raycast_stamp : vol->raycast_stamp;
+    unsigned long long *count = &w.state->footprint;
+    hipError_t e = fill_u32(w.mark_bits, vol->layout.bitmap_words, 0u, stream);
+    if (e == hipSuccess) e = fill_u32((uint32_t *)count, 2, 0u, stream);
+    if (e == hipSuccess) e = launch_range(w, cam, stamp, stream);
+    if (e == hipSuccess)
+        e = launch_march(w, cam, stamp, vol->ray_group, (float4 *)vertex_dev, (float4 *)normal_dev, stream, true);
+    if (e == hipSuccess) e = launch_count_bits(w.mark_bits, vol->layout.bitmap_words, count, stream);
+    unsigned long long host = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, count, sizeof(host), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return TSDF_EHIP;
+    *blocks_out = host;
+    return TSDF_OK;
 }
 
 tsdf_status tsdf_query_stats(tsdf_volume *vol, tsdf_stats *out)

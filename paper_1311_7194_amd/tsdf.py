@@ -27,7 +27,7 @@ EXPORTED = [
     "tsdf_volume_bytes", "tsdf_create_volume", "tsdf_destroy_volume", "tsdf_reset_volume",
     "tsdf_integrate_frame", "tsdf_raycast", "tsdf_query_stats", "tsdf_export_blocks",
     "tsdf_import_blocks", "tsdf_status_string", "tsdf_set_timing", "tsdf_read_timing",
-    "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast",
+    "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast", "tsdf_raycast_footprint",
     "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
     "tsdf_batch_autotune_raycast",
@@ -98,6 +98,7 @@ def lib():
         L.tsdf_reset_volume.argtypes = [P, P]
         L.tsdf_integrate_frame.argtypes = [P, P, P, P, P, P]
         L.tsdf_raycast.argtypes = [P, P, P, P, P, P]
+        L.tsdf_raycast_footprint.argtypes = [P, P, P, P, P, P, P]
         L.tsdf_query_stats.argtypes = [P, P]
         L.tsdf_export_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P, P]
         L.tsdf_import_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P]
@@ -228,6 +229,23 @@ class Volume:
         _check(lib().tsdf_raycast(self.handle, ctypes.byref(intr), p.ctypes.data_as(ctypes.c_void_p),
                                   _ptr(vertex), _ptr(normal), stream_handle(stream)), "tsdf_raycast")
         return vertex, normal
+
+    def raycast_footprint(self, K, pose, vertex: Optional[torch.Tensor] = None,
+                          normal: Optional[torch.Tensor] = None, stream=None):
+        """(blocks read by the march, vertex, normal); synchronises."""
+        intr = make_intrinsics(K)
+        shape = (intr.height, intr.width, 4)
+        if vertex is None:
+            vertex = torch.empty(shape, dtype=torch.float32, device=self.buffer.device)
+        if normal is None:
+            normal = torch.empty(shape, dtype=torch.float32, device=self.buffer.device)
+        assert vertex.shape == shape and normal.shape == shape
+        p = _pose_array(pose)
+        n = ctypes.c_uint64(0)
+        _check(lib().tsdf_raycast_footprint(self.handle, ctypes.byref(intr), p.ctypes.data_as(ctypes.c_void_p),
+                                            _ptr(vertex), _ptr(normal), ctypes.byref(n), stream_handle(stream)),
+               "tsdf_raycast_footprint")
+        return int(n.value), vertex, normal
 
     def stats(self) -> dict:
         st = Stats()

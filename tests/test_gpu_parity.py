@@ -149,3 +149,28 @@ def test_raycast_bitwise_independent_of_group_and_index(tsdf):
                 assert all(int((v[..., 3] > 0).sum()) > 300 for v, _ in maps)
             for (v, n), (rv, rn) in zip(maps, ref):
                 assert torch.equal(v, rv) and torch.equal(n, rn), (group, dense)
+
+
+def test_raycast_footprint_query(tsdf):
+    """The instrumented raycast gives the same maps and counts each block its
+    march reads once: at least one per hit ray's block, at most all blocks."""
+    spec = small_orbit(width=96, height=72, n_frames=3, G=256, vs=0.008)
+    gv = gpu_volume_for(spec)
+    n0, _, _ = gv.raycast_footprint(spec.K, sequence_frame(spec, 0)[1])
+    assert n0 == 0   # empty volume
+    for k in range(3):
+        d, p = sequence_frame(spec, k)
+        gv.integrate(d.cuda(), spec.K, p)
+    st = gv.stats()
+    _, pose = sequence_frame(spec, 1)
+    for group in (1, 4):
+        gv.set_raycast_group(group)
+        v1, n1 = gv.raycast(spec.K, pose)
+        blocks, v2, n2 = gv.raycast_footprint(spec.K, pose)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, v2) and torch.equal(n1, n2)
+        assert 0 < blocks <= st["allocated_blocks"]
+        # every hit vertex lies in (the stencil of) a block the march read
+        hits = int((v1[..., 3] > 0).sum())
+        print(f"[parity] footprint G={group}: {blocks} of {st['allocated_blocks']} blocks, {hits} hits", flush=True)
+        assert hits > 0
