@@ -436,11 +436,18 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
     slot = __shfl(slot, 0);
     fresh = __shfl(fresh, 0);
     if (slot < 0) return;
+    // the block's bound and box as they stand, loaded ahead of the voxel data
+    uint32_t old_min = kKeyPosInf, old_box = 0;
+    if (lane == 0 && !fresh) {
+        old_min = v.block_min[slot];
+        old_box = v.block_box[slot];
+    }
 
     S *bt = poolT + (size_t)slot * kBlockVoxels + lane;
     S *bp = poolP + (size_t)slot * kBlockVoxels + lane;
-    // lower bound of the block's non-chi values as stored, kept for the raycast
-    uint32_t kmin = kKeyPosInf;
+    // lower bound of the block's non-chi values as stored, and the voxels of
+    // this lane's column that hold a non-chi value now, both kept for the raycast
+    uint32_t kmin = kKeyPosInf, live = 0;
     if (fresh) {
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
@@ -449,6 +456,7 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
             store_s(bp + 64 * z, m ? pk[z] : 0.0f);
             if (m) kmin = min(kmin, order_key(stored_value<S>(Tk[z])));
         }
+        live = vmask;
     } else {
         // phase 5: load every z-slice that holds an update (whole slices:
         // 64 contiguous voxels), then update and store the valid voxels
@@ -469,16 +477,21 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
                 kalman(T[z], P[z], Tk[z], pk[z], v.q_hat);
                 store_s(bt + 64 * z, T[z]);
                 store_s(bp + 64 * z, P[z]);
-                if (fabsf(T[z]) <= 1.0f) kmin = min(kmin, order_key(stored_value<S>(T[z])));
+                if (fabsf(T[z]) <= 1.0f) {
+                    kmin = min(kmin, order_key(stored_value<S>(T[z])));
+                    live |= 1u << z;
+                }
             }
         }
     }
     // the owner wavefront folds its new values into the bound (values only
     // ever lower it, so it stays below the true minimum)
     kmin = wave_min_u32(kmin);
+    const uint32_t box = wave_box(live);
     if (lane == 0) {
-        const uint32_t m = fresh ? kmin : min(v.block_min[slot], kmin);
+        const uint32_t m = min(old_min, kmin);
         v.block_min[slot] = m;
+        v.block_box[slot] = box_union(old_box, box);
         if (v.block_index)
             v.block_index[block_linear(v, bx, by, bz)] = slot | (m > kKeyZero ? kIndexPositive : 0);
     }

@@ -92,20 +92,26 @@ __device__ __forceinline__ void range_block(const VolumeView &v, const Camera &c
     const float R[9] = {(float)cam.R[0], (float)cam.R[1], (float)cam.R[2], (float)cam.R[3], (float)cam.R[4],
                         (float)cam.R[5], (float)cam.R[6], (float)cam.R[7], (float)cam.R[8]};
     const float fx = (float)cam.fx, fy = (float)cam.fy, cx = (float)cam.cx, cy = (float)cam.cy;
-    const float bw = (float)(8.0 * v.vs);
+    // a valid sample's stencil voxels are all non-chi, so its base voxel lies
+    // in its block's box of non-chi voxels: q in [8B + lo, 8B + hi + 1] with
+    // x = origin + (q + 1/2) voxel; a block without such voxels adds nothing
+    const uint32_t box = v.block_box[slot];
+    if (!(box & kBoxValid)) return;
     int bx, by, bz;
     unpack_key(v.pool_keys[slot], bx, by, bz);
-    // stencil-base box of block B: q in [8B, 8B + 8], x = origin + (q + 1/2) voxel;
+    const float bwx = (float)((box_hi(box, 0) - box_lo(box, 0) + 1) * v.vs);
+    const float bwy = (float)((box_hi(box, 1) - box_lo(box, 1) + 1) * v.vs);
+    const float bwz = (float)((box_hi(box, 2) - box_lo(box, 2) + 1) * v.vs);
     // its min corner relative to the camera centre, in double then float
-    const float ox = (float)(v.origin[0] + (8.0 * bx + 0.5) * v.vs - cam.t[0]);
-    const float oy = (float)(v.origin[1] + (8.0 * by + 0.5) * v.vs - cam.t[1]);
-    const float oz = (float)(v.origin[2] + (8.0 * bz + 0.5) * v.vs - cam.t[2]);
+    const float ox = (float)(v.origin[0] + (8.0 * bx + box_lo(box, 0) + 0.5) * v.vs - cam.t[0]);
+    const float oy = (float)(v.origin[1] + (8.0 * by + box_lo(box, 1) + 0.5) * v.vs - cam.t[1]);
+    const float oz = (float)(v.origin[2] + (8.0 * bz + box_lo(box, 2) + 0.5) * v.vs - cam.t[2]);
     float zlo = 3.4e38f, zhi = -3.4e38f, ulo = 3.4e38f, uhi = -3.4e38f, vlo = 3.4e38f, vhi = -3.4e38f;
     bool behind = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const float dx = ox + ((k & 1) ? bw : 0.0f), dy = oy + ((k & 2) ? bw : 0.0f),
-                    dz = oz + ((k & 4) ? bw : 0.0f);
+        const float dx = ox + ((k & 1) ? bwx : 0.0f), dy = oy + ((k & 2) ? bwy : 0.0f),
+                    dz = oz + ((k & 4) ? bwz : 0.0f);
         const float xc = R[0] * dx + R[3] * dy + R[6] * dz;
         const float yc = R[1] * dx + R[4] * dy + R[7] * dz;
         const float zc = R[2] * dx + R[5] * dy + R[8] * dz;

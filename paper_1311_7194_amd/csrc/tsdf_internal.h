@@ -49,6 +49,7 @@ struct VolumeView {
     unsigned long long *hash;   // hash_slots entries: (slot << 32) | key, ~0 = empty
     uint32_t *pool_keys;        // capacity entries: key of the block in each pool slot
     uint32_t *block_min;        // capacity entries: ordered key of a lower bound of the block's non-chi T
+    uint32_t *block_box;        // capacity entries: bounding box of the block's non-chi voxels (see box_*)
     uint32_t *tile_range;       // raycast: per 8x8 pixel tile (min depth bits, max depth bits)
     uint32_t *pix_range;        // raycast: per kCell x kCell pixel cell (min depth bits, max depth bits)
     uint32_t *mark_bits;        // one bit per virtual block: blocks a footprint query's rays read
@@ -146,6 +147,53 @@ __device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
     }
     atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_HASH_FULL);
     return -1;
+}
+
+// Bounding box of a block's non-chi voxels, local coordinates 0..7: bits
+// 0-8 the low corner (x, y, z, 3 bits each), bits 9-17 the high corner,
+// bit 31 set when the box is not empty.  Boxes only grow (a voxel that
+// returns to chi stays inside), so they stay conservative.
+constexpr uint32_t kBoxValid = 1u << 31;
+
+__host__ __device__ inline uint32_t box_make(int x0, int y0, int z0, int x1, int y1, int z1)
+{
+    return kBoxValid | (uint32_t)x0 | ((uint32_t)y0 << 3) | ((uint32_t)z0 << 6) | ((uint32_t)x1 << 9) |
+           ((uint32_t)y1 << 12) | ((uint32_t)z1 << 15);
+}
+
+__host__ __device__ inline int box_lo(uint32_t b, int axis) { return (int)((b >> (3 * axis)) & 7u); }
+__host__ __device__ inline int box_hi(uint32_t b, int axis) { return (int)((b >> (9 + 3 * axis)) & 7u); }
+
+__host__ __device__ inline uint32_t box_union(uint32_t a, uint32_t b)
+{
+    if (!(a & kBoxValid)) return b;
+    if (!(b & kBoxValid)) return a;
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = box_lo(a, k) < box_lo(b, k) ? box_lo(a, k) : box_lo(b, k);
+        hi[k] = box_hi(a, k) > box_hi(b, k) ? box_hi(a, k) : box_hi(b, k);
+    }
+    return box_make(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
+}
+
+// Box of the voxels of a wavefront's block that `zmask` (bit z: voxel
+// (x, y, z) of this lane's column, lane = x + 8 y) marks; 0 when none.
+__device__ inline uint32_t wave_box(uint32_t zmask)
+{
+    const unsigned long long L = __ballot(zmask != 0u);
+    if (!L) return 0u;
+    uint32_t zb = 0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) zb |= (__ballot((zmask >> z) & 1u) != 0ull ? 1u : 0u) << z;
+    uint32_t xb = 0, yb = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const uint32_t row = (uint32_t)(L >> (8 * r)) & 0xffu;
+        xb |= row;
+        yb |= (row != 0u ? 1u : 0u) << r;
+    }
+    return box_make(__builtin_ctz(xb), __builtin_ctz(yb), __builtin_ctz(zb), 31 - __builtin_clz(xb),
+                    31 - __builtin_clz(yb), 31 - __builtin_clz(zb & 0xffu));
 }
 
 // Largest pool: slot * 512 + voxel stays below 2^31 (32-bit pool offsets).

@@ -83,17 +83,23 @@ __global__ __launch_bounds__(256) void import_kernel(VolumeView v, const int32_t
     if (slot < 0) return;
     S *dT = (S *)v.poolT + (size_t)slot * kBlockVoxels;
     S *dP = (S *)v.poolP + (size_t)slot * kBlockVoxels;
-    uint32_t kmin = kKeyPosInf;
+    uint32_t kmin = kKeyPosInf, zmask = 0;
+    // lane = x + 8 y holds the column of voxels lane + 64 z
     for (int k = lane; k < kBlockVoxels; k += 64) {
         const S t = T[(size_t)w * kBlockVoxels + k];
         dT[k] = t;
         dP[k] = P[(size_t)w * kBlockVoxels + k];
         const float f = (float)t;
-        if (fabsf(f) <= 1.0f) kmin = min(kmin, order_key(f));
+        if (fabsf(f) <= 1.0f) {
+            kmin = min(kmin, order_key(f));
+            zmask |= 1u << (k >> 6);
+        }
     }
     kmin = wave_min_u32(kmin);
+    const uint32_t box = wave_box(zmask);
     if (lane == 0) {
         v.block_min[slot] = kmin;
+        v.block_box[slot] = box;
         if (v.block_index) v.block_index[block_linear(v, bx, by, bz)] = slot | (kmin > kKeyZero ? kIndexPositive : 0);
     }
 }
@@ -115,7 +121,7 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // ------------------------------------------------------------ layout
 
 struct Layout {
-    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, tile_range, pix_range, mark_bits,
+    uint64_t state, ctr, hash, occupancy, block_index, cand_bits, cand_list, pixmap, pool_keys, block_min, block_box, tile_range, pix_range, mark_bits,
         poolT, poolP, total;
     uint64_t bitmap_words, tile_words, nblocks;
 };
@@ -172,6 +178,8 @@ static Layout layout_of(const tsdf_volume_desc *d)
     L.pool_keys = off;
     off = align256(off + 4ull * d->capacity_blocks);
     L.block_min = off;
+    off = align256(off + 4ull * d->capacity_blocks);
+    L.block_box = off;
     off = align256(off + 4ull * d->capacity_blocks);
     L.tile_words = (uint64_t)((d->max_width + 7) / 8) * (uint64_t)((d->max_height + 7) / 8);
     L.tile_range = off;
@@ -387,6 +395,7 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     w.block_min = (uint32_t *)(v->base + L.block_min);
     w.tile_range = (uint32_t *)(v->base + L.tile_range);
     w.pix_range = (uint32_t *)(v->base + L.pix_range);
+    w.block_box = (uint32_t *)(v->base + L.block_box);
     w.mark_bits = (uint32_t *)(v->base + L.mark_bits);
     w.max_width = desc->max_width;
     w.max_height = desc->max_height;
