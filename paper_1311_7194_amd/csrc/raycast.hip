@@ -10,10 +10,11 @@
 // Range shrinking.  The paper rasterises the faces of occupied blocks into
 // per-pixel start and end textures so that rays only traverse the depth span
 // of occupied blocks.  Here a compute pass does the same at the granularity
-// of 4x4-pixel cells: for every allocated block it projects the box in which
-// that block is the base of the interpolation stencil and widens the
+// of 4x4-pixel cells: for every allocated block it projects the box of
+// stencil bases that can give a valid sample (the bounding box of the
+// block's non-chi voxels, extended by one voxel upwards) and widens the
 // [min, max] camera depth of every cell holding a pixel centre the box's
-// projection may cover (blocks whose projection spans more than 64 cells
+// projection may cover (boxes whose projection spans more than 64 cells
 // widen whole 8x8-pixel tiles instead).  Every valid sample lies in such a
 // box, so starting and ending each ray at its cell's span (joined with its
 // tile's) skips only invalid samples.
