@@ -30,34 +30,8 @@ constexpr int kLdsList = 1024;        // unique keys held for the global pass
 constexpr int kSubRanges = 4;         // depth sub-intervals of a pixel's frustum cell
 
 // Marks `key` as a candidate of this frame; the first marker appends it to
-// the candidate list.  Called by the active lanes of one wavefront.
-__device__ inline void global_candidate(const VolumeView &v, uint32_t key)
-{
-    int bx, by, bz;
-    unpack_key(key, bx, by, bz);
-    uint64_t b = block_linear(v, bx, by, bz);
-    uint32_t bit = 1u << (b & 31);
-    uint32_t old = atomicOr(&v.cand_bits[b >> 5], bit);
-    bool fresh = !(old & bit);
-    unsigned long long m = __ballot(fresh);
-    if (!m) return;
-    int lane = __lane_id();
-    int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&v.state->cand_count, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (fresh) {
-        uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (idx < v.max_candidates) {
-            v.cand_list[idx] = key;
-        } else {
-            atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
-            atomicAnd(&v.cand_bits[b >> 5], ~bit);
-        }
-    }
-}
-
-// Single-lane version for keys that did not fit the LDS set.
+// the candidate list.  Used, one lane at a time, for keys that did not fit
+// the LDS set; the tile's other keys are appended together (prep_body).
 __device__ inline void global_candidate_lane(const VolumeView &v, uint32_t key, int bx, int by, int bz)
 {
     uint64_t b = block_linear(v, bx, by, bz);
@@ -203,7 +177,37 @@ __device__ __forceinline__ void prep_body(const VolumeView &v, const float *__re
     }
     __syncthreads();
     const uint32_t n = min(n_list, (uint32_t)kLdsList);
-    for (uint32_t k = tid; k < n; k += 256) global_candidate(v, list[k]);
+    if (n == 0) return;
+    // Keys this tile is first to mark are compacted into the (now unused)
+    // set and appended with one counter update per tile: a counter update
+    // per wavefront makes every tile of the frame queue on one address.
+    __shared__ uint32_t n_fresh, base;
+    if (tid == 0) n_fresh = 0;
+    __syncthreads();
+    for (uint32_t k = tid; k < n; k += 256) {
+        const uint32_t key = list[k];
+        int bx, by, bz;
+        unpack_key(key, bx, by, bz);
+        const uint64_t b = block_linear(v, bx, by, bz);
+        const uint32_t bit = 1u << (b & 31);
+        if (!(atomicOr(&v.cand_bits[b >> 5], bit) & bit)) set[atomicAdd(&n_fresh, 1u)] = key;
+    }
+    __syncthreads();
+    if (tid == 0 && n_fresh) base = atomicAdd(&v.state->cand_count, n_fresh);
+    __syncthreads();
+    for (uint32_t k = tid; k < n_fresh; k += 256) {
+        const uint32_t key = set[k];
+        const uint32_t idx = base + k;
+        if (idx < v.max_candidates) {
+            v.cand_list[idx] = key;
+        } else {
+            int bx, by, bz;
+            unpack_key(key, bx, by, bz);
+            const uint64_t b = block_linear(v, bx, by, bz);
+            atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_CAND_FULL);
+            atomicAnd(&v.cand_bits[b >> 5], ~(1u << (b & 31)));
+        }
+    }
 }
 
 // ---------------------------------------------------------------- fuse
