@@ -241,9 +241,9 @@ static hipError_t enqueue_step(tsdf_batch *b, int32_t noise_kind, hipStream_t s)
     else
         hipLaunchKernelGGL(batch_prep<false>, dim3(b->prep_total), dim3(256), 0, s, b->dev, n);
     if (b->storage == TSDF_F16)
-        hipLaunchKernelGGL(batch_fuse<__half>, dim3(4096), dim3(256), 0, s, b->dev, n);
+        hipLaunchKernelGGL(batch_fuse<__half>, dim3(kFuseGrid), dim3(256), 0, s, b->dev, n);
     else
-        hipLaunchKernelGGL(batch_fuse<float>, dim3(4096), dim3(256), 0, s, b->dev, n);
+        hipLaunchKernelGGL(batch_fuse<float>, dim3(kFuseGrid), dim3(256), 0, s, b->dev, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return enqueue_raycast(b, s);

@@ -321,6 +321,9 @@ __device__ __forceinline__ float stored_value<float>(float x) { return x; }
 template <>
 __device__ __forceinline__ float stored_value<__half>(float x) { return __half2float(__float2half_rn(x)); }
 
+// Workgroups (of four wavefronts) of the persistent fusion grid.
+constexpr uint32_t kFuseGrid = 2560;
+
 // Event counts a wavefront accumulates over the candidates it processes.
 struct FuseAcc {
     uint32_t upd = 0, fresh = 0, nw = 0, touched = 0;
