@@ -221,6 +221,29 @@ def render_depth(scene: Scene, K: Intrinsics, pose: np.ndarray, near=0.0, far=ma
     return torch.where(ok, lam, torch.zeros_like(lam))
 
 
+def render_model_maps(scene: Scene, K: Intrinsics, pose: np.ndarray, near=0.0, far=math.inf, eps=1e-6):
+    """Exact vertex and normal maps of the scene seen from `pose`, in the
+    layout a raycast produces: float32 [H, W, 4] each, world coordinates,
+    w = 1 where the pixel's ray hits a surface and 0 elsewhere.  The normal
+    is the normalised central-difference gradient of the scene's signed
+    distance (step eps metres), so it faces out of the solids."""
+    o, d = pixel_rays(K, pose)
+    lam = ray_entry(scene, o, d)
+    zc = lam   # d has camera-z component 1, so lam is the camera depth
+    ok = torch.isfinite(lam) & (zc >= near) & (zc <= far)
+    x = o + torch.where(ok, lam, torch.zeros_like(lam))[..., None] * d
+    g = torch.zeros_like(x)
+    for a in range(3):
+        e = torch.zeros(3, dtype=F64)
+        e[a] = eps
+        g[..., a] = scene_sdf(scene, x + e) - scene_sdf(scene, x - e)
+    g = g / torch.linalg.norm(g, dim=-1, keepdim=True).clamp_min(1e-300)
+    w = ok.to(F64)[..., None]
+    vert = torch.cat([x * w, w], -1).to(torch.float32)
+    nrm = torch.cat([g * w, w], -1).to(torch.float32)
+    return vert, nrm
+
+
 # ---------------------------------------------------------------------------
 # Signed distances (positive outside) for ground truth.
 
