@@ -139,6 +139,54 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
     return res
 
 
+ICP_BYTES_PER_PIXEL = 36   # live depth (4 B) + one model vertex and normal (2 x 16 B) per pixel
+
+
+def run_icp(res, spec, pairs=20, iters=10):
+    """Point-to-plane ICP on the fused volume: for frame pairs (k, k+1), the
+    model maps are the raycast at frame k's pose and frame k+1's depth is
+    registered from frame k's pose with `iters` chained iterations.  The
+    timed region holds only the iterations (HIP events on the stream they run on)."""
+    from paper_1311_7194_amd import Icp
+
+    vol = res["_vol"]
+    depths, poses = res["_frames"]
+    K = spec.K
+    icp = Icp(K, dist_max=0.1, cos_min=math.cos(math.radians(30.0)), max_iters=iters)
+    vert = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(vert)
+    n = min(pairs, len(depths) - 1)
+    total_ms, n_pairs, err0, err1 = 0.0, 0, [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for k in range(-1, n):          # the first pair (k = -1 -> frame 0) is a warm-up
+        kk = max(k, 0)
+        vol.raycast(K, poses[kk], vert, nrm)
+        e0.record()
+        icp.run(depths[kk + 1], vert, nrm, poses[kk], poses[kk], iters)
+        e1.record()
+        torch.cuda.synchronize()
+        if k < 0:
+            continue
+        total_ms += e0.elapsed_time(e1)
+        n_pairs += sum(icp.result(i)["N"] for i in range(iters))
+        est = icp.result(iters - 1)["pose"]
+        err0.append(float(np.abs(poses[kk][:, 3] - poses[kk + 1][:, 3]).max()))
+        err1.append(float(np.abs(est[:, 3] - poses[kk + 1][:, 3]).max()))
+    it = n * iters
+    us = total_ms * 1e3 / it
+    byts = ICP_BYTES_PER_PIXEL * K.width * K.height
+    gbs = byts / (us * 1e-6) / 1e9
+    return {"workload": res["workload"], "stage": "icp", "frame_pairs": n, "iterations_per_pair": iters,
+            "us_per_iteration": round(us, 2), "pairs_per_iteration": n_pairs // it,
+            "mpix_s": round(K.width * K.height / us, 1),
+            "translation_error_m": {"start_mean": round(float(np.mean(err0)), 5),
+                                    "end_mean": round(float(np.mean(err1)), 5)},
+            "roofline": {"kernel": "icp iteration (icp_pairs_kernel + icp_solve_kernel)", "bound": "hbm",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "bytes_per_launch": byts,
+                         "avg_launch_us": round(us, 2)}}
+
+
 def raycast_footprint(res, spec, storage, steps, noise=None):
     """Replays the timed sequence outside the timed region with the
     instrumented raycast and returns the mean number of blocks whose voxels a
@@ -374,6 +422,8 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=300)
     ap.add_argument("--batch", type=int, default=1, help="also run the 16-scene batched workload")
     ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
+    ap.add_argument("--icp", type=int, default=1, help="also time point-to-plane ICP on the fused volume")
+    ap.add_argument("--icp-iters", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size reference "
@@ -438,6 +488,10 @@ def main():
                          "updates_per_frame": rl["updates"] // rl["frames"]})
         log(json.dumps({k: v for k, v in rl.items() if not k.startswith("_")}))
         del rl
+    if args.icp:
+        ri = run_icp(res, spec, iters=args.icp_iters)
+        log(json.dumps(ri))
+        variants.append(ri)
     if args.variants and args.config != "c3":
         spec3 = make_spec("c3", args.variant_steps)
         r32 = run_sequence(spec3, 0, args.variant_steps, 3)

@@ -6,5 +6,5 @@ device tensors.
 """
 
 from .tsdf import (  # noqa: F401
-    F16, F32, NOISE_CONSTANT, NOISE_MLP, NOISE_QUADRATIC, Batch, TsdfError, Volume, lib, LIB_PATH,
+    F16, F32, NOISE_CONSTANT, NOISE_MLP, NOISE_QUADRATIC, Batch, Icp, TsdfError, Volume, lib, LIB_PATH,
 )

@@ -30,7 +30,7 @@ EXPORTED = [
     "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast", "tsdf_raycast_footprint",
     "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
-    "tsdf_batch_autotune_raycast",
+    "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step",
 ]
 
 
@@ -119,8 +119,12 @@ def lib():
         L.tsdf_batch_get_raycast_group.argtypes = [P]
         L.tsdf_batch_step.argtypes = [P, P, P, P, P, P, P]
         L.tsdf_batch_autotune_raycast.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
+        L.tsdf_icp_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.tsdf_icp_workspace_bytes.restype = ctypes.c_uint64
+        L.tsdf_icp_step.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_uint64, P, P]
         for name in EXPORTED:
-            if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy"):
+            if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy",
+                            "tsdf_icp_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -393,3 +397,67 @@ class Batch:
                                                  self._np, int(reps), stream_handle(stream), ctypes.byref(best),
                                                  ctypes.byref(ms)), "tsdf_batch_autotune_raycast")
         return int(best.value), float(ms.value)
+
+
+class IcpParams(ctypes.Structure):
+    _fields_ = [("dist_max", ctypes.c_double), ("cos_min", ctypes.c_double), ("theta", ctypes.c_double),
+                ("shrink", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class IcpResult(ctypes.Structure):
+    _fields_ = [("pose", ctypes.c_double * 12), ("x", ctypes.c_double * 6), ("lam", ctypes.c_double * 6),
+                ("C", ctypes.c_double * 36), ("b", ctypes.c_double * 6), ("m", ctypes.c_double * 3),
+                ("S", ctypes.c_double * 3), ("residual2", ctypes.c_double), ("pairs", ctypes.c_int64),
+                ("kept", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+ICP_RESULT_DOUBLES = ctypes.sizeof(IcpResult) // 8
+
+
+class Icp:
+    """Point-to-plane ICP (tsdf_icp.h) for depth maps of one size.
+
+    Holds the device workspace and a device array of result records; the
+    pose estimate stays on the device between iterations."""
+
+    def __init__(self, K, dist_max: float = 0.02, cos_min: float = 0.9396926207859084, theta: float = 0.005,
+                 shrink: bool = True, max_iters: int = 32, device: str = "cuda"):
+        self.K = make_intrinsics(K)
+        self.params = IcpParams(float(dist_max), float(cos_min), float(theta), 1 if shrink else 0, 0)
+        nbytes = int(lib().tsdf_icp_workspace_bytes(self.K.width, self.K.height))
+        if nbytes == 0:
+            raise TsdfError(EINVAL, "tsdf_icp_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.results = torch.zeros((max_iters, ICP_RESULT_DOUBLES), dtype=torch.float64, device=device)
+        self.pose0 = torch.zeros(12, dtype=torch.float64, device=device)
+
+    def step(self, depth: torch.Tensor, model_vertex: torch.Tensor, model_normal: torch.Tensor, model_pose,
+             pose_dev: torch.Tensor, k: int = 0, stream=None) -> torch.Tensor:
+        """One iteration from the device pose `pose_dev` (12 float64); writes
+        result record k and returns the device view of its pose."""
+        mp = _pose_array(model_pose)
+        _check(lib().tsdf_icp_step(_ptr(depth), ctypes.byref(self.K), _ptr(model_vertex), _ptr(model_normal),
+                                   mp.ctypes.data_as(ctypes.c_void_p), _ptr(pose_dev), ctypes.byref(self.params),
+                                   _ptr(self.workspace), ctypes.c_uint64(self.workspace.numel()),
+                                   _ptr(self.results[k]), stream_handle(stream)), "tsdf_icp_step")
+        return self.results[k, :12]
+
+    def run(self, depth: torch.Tensor, model_vertex: torch.Tensor, model_normal: torch.Tensor, model_pose, pose,
+            iters: int, stream=None) -> torch.Tensor:
+        """`iters` chained iterations from the host pose `pose`; returns the
+        device pose after the last one (record iters - 1)."""
+        if not 1 <= iters <= self.results.shape[0]:
+            raise ValueError("iters")
+        self.pose0.copy_(torch.as_tensor(_pose_array(pose)))
+        cur = self.pose0
+        for k in range(iters):
+            cur = self.step(depth, model_vertex, model_normal, model_pose, cur, k, stream)
+        return cur
+
+    def result(self, k: int = 0) -> dict:
+        """Record k as a dict (synchronises)."""
+        raw = self.results[k].cpu().numpy().tobytes()
+        r = IcpResult.from_buffer_copy(raw)
+        return dict(pose=np.array(r.pose).reshape(3, 4), x=np.array(r.x), lam=np.array(r.lam),
+                    C=np.array(r.C).reshape(6, 6), b=np.array(r.b), m=np.array(r.m), S=np.array(r.S),
+                    residual2=r.residual2, N=int(r.pairs), kept=int(r.kept))

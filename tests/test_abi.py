@@ -112,3 +112,34 @@ def test_batch_host_validation(lib):
     assert lib.tsdf_batch_set_raycast_group(None, 4) == T.EINVAL
     assert lib.tsdf_batch_get_raycast_group(None) == 0
     lib.tsdf_batch_destroy(None)
+
+
+def test_icp_host_validation(lib):
+    assert lib.tsdf_icp_workspace_bytes(0, 480) == 0
+    assert lib.tsdf_icp_workspace_bytes(640, 16385) == 0
+    ws = lib.tsdf_icp_workspace_bytes(640, 480)
+    assert ws == 1024 * 36 * 8 and lib.tsdf_icp_workspace_bytes(16, 16) == 36 * 8
+    assert ctypes.sizeof(T.IcpResult) == 600 and ctypes.sizeof(T.IcpParams) == 32
+    K = T.Intrinsics(525.0, 525.0, 319.5, 239.5, 640, 480)
+    pose = (ctypes.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+
+    def call(K=K, pose=pose, params=None, ws_bytes=ws, null=None):
+        prm = params or T.IcpParams(0.02, 0.9, 0.005, 1, 0)
+        args = [fake, ctypes.byref(K), fake, fake, pose, fake, ctypes.byref(prm), fake, ctypes.c_uint64(ws_bytes),
+                fake, None]
+        if null is not None:
+            args[null] = None
+        return lib.tsdf_icp_step(*args)
+
+    for k in (0, 1, 2, 3, 4, 5, 6, 7, 9):
+        assert call(null=k) == T.EINVAL, k
+    assert call(ws_bytes=ws - 8) == T.EINVAL
+    assert call(K=T.Intrinsics(0.0, 525.0, 319.5, 239.5, 640, 480)) == T.EINVAL
+    assert call(K=T.Intrinsics(525.0, 525.0, 319.5, 239.5, 0, 480)) == T.EINVAL
+    assert call(pose=(ctypes.c_double * 12)(2, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)) == T.EINVAL
+    assert call(pose=(ctypes.c_double * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)) == T.EINVAL
+    for bad in (T.IcpParams(0.0, 0.9, 0.005, 1, 0), T.IcpParams(float("nan"), 0.9, 0.005, 1, 0),
+                T.IcpParams(0.02, 1.5, 0.005, 1, 0), T.IcpParams(0.02, 0.9, float("inf"), 1, 0),
+                T.IcpParams(0.02, 0.9, 0.005, 2, 0)):
+        assert call(params=bad) == T.EINVAL
