@@ -26,10 +26,12 @@ namespace tsdf {
 namespace {
 
 constexpr int kIcpThreads = 256;
-constexpr int kIcpMaxGroups = 1024;
-constexpr int kSums = 29;      // 21 upper-triangle entries, 6 right-hand sides, e^2, pair count
-constexpr int kVals = 35;      // + box minimum (3) and maximum (3)
-constexpr int kStride = 36;    // doubles per partial
+constexpr int kIcpMaxGroups = 512;
+// Per-workgroup partials, stored value-major ([kPartial][groups]):
+//   0..20 upper triangle of sum g g^T, g = (p x n, n); 21..26 sum g e;
+//   27 sum e^2; 28 pair count; 29..31 zero;
+//   32..34 -min and 35..37 max of the kept p and q per axis; 38, 39 unused.
+constexpr int kPartial = 40;
 
 struct IcpArgs {
     double Rm[9], tm[3];       // model pose, camera to world
@@ -43,34 +45,59 @@ struct IcpArgs {
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }
 
-// Reduces the kVals values of every lane of the workgroup into lane 0 of
-// wave 0: sums for the first kSums, minimum and maximum for the box.
-__device__ __forceinline__ void block_reduce(double v[kVals], double (*lds)[kVals])
+struct ReduceLds {
+    double s[kIcpThreads / 64][32];
+    double x[kIcpThreads / 64][8];
+    double tot[kPartial];
+};
+
+// Workgroup reduction of 32 sums and 8 maxima per lane into L.tot (visible
+// to every thread on return).  Within a wavefront, recursive halving: at
+// each exchange a lane keeps one half of its values and sends the other, so
+// the sums take 32 exchanges instead of 6 per value.  Afterwards lanes 2m and
+// 2m + 1 hold the wavefront's total of sum m, and lanes 8m..8m + 7 its
+// maximum m.
+__device__ __forceinline__ void block_reduce(const double s[32], const double x[8], ReduceLds &L)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    double h16[16], h8[8], h4[4], h2[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int k = 0; k < 16; ++k) h16[k] = (b5 ? s[k + 16] : s[k]) + __shfl_xor(b5 ? s[k] : s[k + 16], 32);
 #pragma unroll
-        for (int k = 0; k < kVals; ++k) {
-            const double o = __shfl_xor(v[k], off);
-            v[k] = k < kSums ? v[k] + o : (k < kSums + 3 ? fmin(v[k], o) : fmax(v[k], o));
-        }
-    }
-    if (lane == 0)
+    for (int k = 0; k < 8; ++k) h8[k] = (b4 ? h16[k + 8] : h16[k]) + __shfl_xor(b4 ? h16[k] : h16[k + 8], 16);
 #pragma unroll
-        for (int k = 0; k < kVals; ++k) lds[wave][k] = v[k];
+    for (int k = 0; k < 4; ++k) h4[k] = (b3 ? h8[k + 4] : h8[k]) + __shfl_xor(b3 ? h8[k] : h8[k + 4], 8);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) h2[k] = (b2 ? h4[k + 2] : h4[k]) + __shfl_xor(b2 ? h4[k] : h4[k + 2], 4);
+    double h1 = (b1 ? h2[1] : h2[0]) + __shfl_xor(b1 ? h2[0] : h2[1], 2);
+    h1 += __shfl_xor(h1, 1);
+    if (!(lane & 1)) L.s[wave][lane >> 1] = h1;
+    double g4[4], g2[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g4[k] = fmax(b5 ? x[k + 4] : x[k], __shfl_xor(b5 ? x[k] : x[k + 4], 32));
+#pragma unroll
+    for (int k = 0; k < 2; ++k) g2[k] = fmax(b4 ? g4[k + 2] : g4[k], __shfl_xor(b4 ? g4[k] : g4[k + 2], 16));
+    double g1 = fmax(b3 ? g2[1] : g2[0], __shfl_xor(b3 ? g2[0] : g2[1], 8));
+    g1 = fmax(g1, __shfl_xor(g1, 4));
+    g1 = fmax(g1, __shfl_xor(g1, 2));
+    g1 = fmax(g1, __shfl_xor(g1, 1));
+    if (!(lane & 7)) L.x[wave][lane >> 3] = g1;
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int w = 1; w < kIcpThreads / 64; ++w)
-#pragma unroll
-            for (int k = 0; k < kVals; ++k)
-                v[k] = k < kSums ? v[k] + lds[w][k] : (k < kSums + 3 ? fmin(v[k], lds[w][k]) : fmax(v[k], lds[w][k]));
+    const int t = threadIdx.x;
+    if (t < 32)
+        L.tot[t] = (L.s[0][t] + L.s[1][t]) + (L.s[2][t] + L.s[3][t]);
+    else if (t < kPartial)
+        L.tot[t] = fmax(fmax(L.x[0][t - 32], L.x[1][t - 32]), fmax(L.x[2][t - 32], L.x[3][t - 32]));
+    __syncthreads();
 }
 
-__device__ __forceinline__ void init_vals(double v[kVals])
+__device__ __forceinline__ void init_acc(double s[32], double x[8])
 {
 #pragma unroll
-    for (int k = 0; k < kVals; ++k) v[k] = k < kSums ? 0.0 : (k < kSums + 3 ? INFINITY : -INFINITY);
+    for (int k = 0; k < 32; ++k) s[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = -INFINITY;
 }
 
 __global__ __launch_bounds__(kIcpThreads) void icp_pairs_kernel(const float *__restrict__ depth,
@@ -80,7 +107,7 @@ __global__ __launch_bounds__(kIcpThreads) void icp_pairs_kernel(const float *__r
                                                                 double *__restrict__ partial)
 {
 #pragma clang fp contract(off)
-    __shared__ double lds[kIcpThreads / 64][kVals];
+    __shared__ ReduceLds L;
     const int W = a.width, H = a.height;
     double Rc[9], tc[3];
 #pragma unroll
@@ -89,12 +116,11 @@ __global__ __launch_bounds__(kIcpThreads) void icp_pairs_kernel(const float *__r
         for (int c = 0; c < 3; ++c) Rc[3 * r + c] = pose[4 * r + c];
         tc[r] = pose[4 * r + 3];
     }
-    double v[kVals];
-    init_vals(v);
-    const long long npix = (long long)W * H;
-    for (long long pix = (long long)blockIdx.x * kIcpThreads + threadIdx.x; pix < npix;
-         pix += (long long)gridDim.x * kIcpThreads) {
-        const int i = (int)(pix % W), j = (int)(pix / W);
+    double v[32], bx[8];
+    init_acc(v, bx);
+    const uint32_t npix = (uint32_t)W * (uint32_t)H;   // at most 16384^2 < 2^32
+    for (uint32_t pix = blockIdx.x * kIcpThreads + threadIdx.x; pix < npix; pix += gridDim.x * kIcpThreads) {
+        const int j = (int)(pix / (uint32_t)W), i = (int)(pix - (uint32_t)j * (uint32_t)W);
         if (i + 1 >= W || j + 1 >= H) continue;
         const float d0 = depth[pix], dr = depth[pix + 1], dd = depth[pix + W];
         if (!(depth_ok(d0) && depth_ok(dr) && depth_ok(dd))) continue;
@@ -148,74 +174,138 @@ __global__ __launch_bounds__(kIcpThreads) void icp_pairs_kernel(const float *__r
         v[28] += 1.0;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            v[kSums + r] = fmin(v[kSums + r], fmin(p[r], q[r]));
-            v[kSums + 3 + r] = fmax(v[kSums + 3 + r], fmax(p[r], q[r]));
+            bx[r] = fmax(bx[r], fmax(-p[r], -q[r]));
+            bx[3 + r] = fmax(bx[3 + r], fmax(p[r], q[r]));
         }
     }
-    block_reduce(v, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < kVals; ++k) partial[(size_t)blockIdx.x * kStride + k] = v[k];
+    block_reduce(v, bx, L);
+    if (threadIdx.x < kPartial) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = L.tot[threadIdx.x];
 }
 
-// Eigen-decomposition of the symmetric 6x6 matrix A (destroyed) by cyclic
-// Jacobi rotations: A V = V diag(lam).
-__device__ void jacobi6(double A[36], double V[36], double lam[6])
+// Parallel cyclic Jacobi for a symmetric 6x6 matrix on one wavefront.  Lane
+// l < 36 holds element (l / 6, l % 6) of A and of the eigenvector matrix V.
+// A sweep is five rounds of three disjoint plane rotations: in round k the
+// index x5 = 3k mod 5 pairs with 5 and the others as (x5 + 1, x5 + 4) and
+// (x5 + 2, x5 + 3) mod 5 (indices x, y < 5 pair when x + y = k mod 5), which
+// covers all 15 pairs.  Disjoint rotations commute and do not touch each
+// other's 2x2 blocks, so a round applies its three at once: A <- J^T A J,
+// V <- V J.  The pivots are read out of their lanes as wave-uniform values
+// and every lane computes the three rotations itself.
+__device__ __forceinline__ double lane_value(double x, int lane)
 {
-    for (int k = 0; k < 36; ++k) V[k] = (k % 7 == 0) ? 1.0 : 0.0;
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Reciprocal and reciprocal square root to about an ulp: the hardware
+// estimate and two Newton steps.  The rotations only have to (nearly) zero
+// their pivot and stay orthogonal, which c = 1/sqrt(1 + t^2), s = t c does
+// to rounding whatever the accuracy of t.
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double fast_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+
+__device__ __forceinline__ void plane_rotation(double app, double aqq, double apq, double &c, double &s)
+{
+    if (apq == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
+    const double th = 0.5 * (aqq - app) * fast_rcp(apq);
+    const double at = fabs(th);
+    // t = sign(th) / (|th| + sqrt(th^2 + 1)), with sqrt(h) = h / sqrt(h);
+    // beyond |th| = 1e100 (where th^2 would overflow) t = 1 / (2 |th|) to rounding
+    const double h = at < 1e100 ? fma(at, at, 1.0) : 1.0;
+    const double den = at < 1e100 ? at + h * fast_rsqrt(h) : 2.0 * at;
+    const double t = (th >= 0.0 ? 1.0 : -1.0) * fast_rcp(den);
+    c = fast_rsqrt(fma(t, t, 1.0));
+    s = t * c;
+}
+
+// Called by the 64 lanes of one wavefront; sA (read) and sV, sLam (written) in LDS.
+__device__ void jacobi6_wave(const double *sA, double *sV, double *sLam)
+{
+    const int lane = threadIdx.x & 63;
+    const bool own = lane < 36;
+    const int r = own ? lane / 6 : 0, c = own ? lane % 6 : 0;
+    double a = own ? sA[lane] : 0.0;
+    double v = own && r == c ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 64; ++sweep) {
         double off = 0.0, diag = 0.0;
-        for (int r = 0; r < 6; ++r) {
-            diag += A[7 * r] * A[7 * r];
-            for (int c = r + 1; c < 6; ++c) off += A[6 * r + c] * A[6 * r + c];
-        }
-        if (!(off > 1e-36 * diag)) break;
-        for (int p = 0; p < 5; ++p)
+        for (int p = 0; p < 6; ++p) {
+            const double d = lane_value(a, 7 * p);
+            diag += d * d;
             for (int q = p + 1; q < 6; ++q) {
-                const double apq = A[6 * p + q];
-                if (apq == 0.0) continue;
-                // rotation in the (p, q) plane that zeroes A[p][q]
-                const double th = (A[7 * q] - A[7 * p]) / (2.0 * apq);
-                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < 6; ++k) {   // A <- A J
-                    const double akp = A[6 * k + p], akq = A[6 * k + q];
-                    A[6 * k + p] = c * akp - s * akq;
-                    A[6 * k + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < 6; ++k) {   // A <- J^T A
-                    const double apk = A[6 * p + k], aqk = A[6 * q + k];
-                    A[6 * p + k] = c * apk - s * aqk;
-                    A[6 * q + k] = s * apk + c * aqk;
-                }
-                A[6 * p + q] = A[6 * q + p] = 0.0;
-                for (int k = 0; k < 6; ++k) {   // V <- V J
-                    const double vkp = V[6 * k + p], vkq = V[6 * k + q];
-                    V[6 * k + p] = c * vkp - s * vkq;
-                    V[6 * k + q] = s * vkp + c * vkq;
-                }
+                const double o = lane_value(a, 6 * p + q);
+                off += o * o;
             }
+        }
+        if (!(off > 1e-26 * diag)) break;   // off-diagonal norm below 1e-13 of the diagonal's
+        for (int k = 0; k < 5; ++k) {
+            const int x5 = (3 * k) % 5;
+            int P[3], Q[3];
+            P[0] = x5;
+            Q[0] = 5;
+            P[1] = min((x5 + 1) % 5, (x5 + 4) % 5);
+            Q[1] = max((x5 + 1) % 5, (x5 + 4) % 5);
+            P[2] = min((x5 + 2) % 5, (x5 + 3) % 5);
+            Q[2] = max((x5 + 2) % 5, (x5 + 3) % 5);
+            double cs[3], sn[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                plane_rotation(lane_value(a, 7 * P[i]), lane_value(a, 7 * Q[i]), lane_value(a, 6 * P[i] + Q[i]), cs[i],
+                               sn[i]);
+            // this lane's row and column: pair, partner, and column of J
+            // (J[x][x] = cos, J[partner][x] = -sin for the pair's smaller index, +sin otherwise)
+            const int ir = (r == P[0] || r == Q[0]) ? 0 : ((r == P[1] || r == Q[1]) ? 1 : 2);
+            const int ic = (c == P[0] || c == Q[0]) ? 0 : ((c == P[1] || c == Q[1]) ? 1 : 2);
+            const int pr = ir == 0 ? P[0] : (ir == 1 ? P[1] : P[2]), qr = ir == 0 ? Q[0] : (ir == 1 ? Q[1] : Q[2]);
+            const int pc = ic == 0 ? P[0] : (ic == 1 ? P[1] : P[2]), qc = ic == 0 ? Q[0] : (ic == 1 ? Q[1] : Q[2]);
+            const int r2 = r == pr ? qr : pr, c2 = c == pc ? qc : pc;
+            const double cr = ir == 0 ? cs[0] : (ir == 1 ? cs[1] : cs[2]);
+            const double cc = ic == 0 ? cs[0] : (ic == 1 ? cs[1] : cs[2]);
+            const double snr = ir == 0 ? sn[0] : (ir == 1 ? sn[1] : sn[2]);
+            const double snc = ic == 0 ? sn[0] : (ic == 1 ? sn[1] : sn[2]);
+            const double sr = r == pr ? -snr : snr, sc = c == pc ? -snc : snc;
+            const double a_rc2 = __shfl(a, 6 * r + c2), a_r2c = __shfl(a, 6 * r2 + c), a_r2c2 = __shfl(a, 6 * r2 + c2);
+            const double v_rc2 = __shfl(v, 6 * r + c2);
+            const double an = (cr * cc * a + cr * sc * a_rc2) + (sr * cc * a_r2c + sr * sc * a_r2c2);
+            a = c == r2 ? 0.0 : an;   // the rotated pair's off-diagonal entries
+            v = v * cc + v_rc2 * sc;
+        }
     }
-    for (int k = 0; k < 6; ++k) lam[k] = A[7 * k];
+    if (own) {
+        sV[lane] = v;
+        if (r == c) sLam[r] = a;
+    }
 }
 
-__global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__restrict__ partial, int groups,
-                                                                const double *__restrict__ pose, IcpArgs a,
-                                                                tsdf_icp_result *__restrict__ res)
-{
-    __shared__ double lds[kIcpThreads / 64][kVals];
-    double v[kVals];
-    init_vals(v);
-    for (int g = threadIdx.x; g < groups; g += kIcpThreads) {
-        const double *pg = partial + (size_t)g * kStride;
-#pragma unroll
-        for (int k = 0; k < kVals; ++k)
-            v[k] = k < kSums ? v[k] + pg[k] : (k < kSums + 3 ? fmin(v[k], pg[k]) : fmax(v[k], pg[k]));
-    }
-    block_reduce(v, lds);
-    if (threadIdx.x != 0) return;
+// The system solved in this iteration (scaled when shrink is set).
+struct IcpSystem {
+    double A[36], b[6], m[3], S[3];
+    double N, e2;
+};
 
-    // unscaled system: blocks Acc = sum c c^T, Acn = sum c n^T, Ann = sum n n^T, and sum g e
+// From the reduced sums: the unscaled blocks Acc = sum c c^T, Acn = sum c n^T,
+// Ann = sum n n^T and sum g e; with shrink, the scaled system by the change
+// of variables c^ = S^-1 (c - M n), M n = m x n:
+//   S^-1 (Acc - Acn M^T - M Acn^T + M Ann M^T) S^-1,  S^-1 (Acn - M Ann),  Ann,
+//   right-hand side -S^-1 (sum c e - M sum n e), -sum n e.
+__device__ void system_of(const double *v, const IcpArgs &a, IcpSystem &sys)
+{
     double A[36];
     int k = 0;
     for (int r = 0; r < 6; ++r)
@@ -226,40 +316,31 @@ __global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__
     double m[3] = {0.0, 0.0, 0.0}, S[3] = {1.0, 1.0, 1.0};
     if (a.shrink && N > 0.0) {
         for (int r = 0; r < 3; ++r) {
-            m[r] = 0.5 * (v[kSums + r] + v[kSums + 3 + r]);
-            const double ext = v[kSums + 3 + r] - v[kSums + r];
+            const double lo = -v[32 + r], hi = v[35 + r];
+            m[r] = 0.5 * (lo + hi);
+            const double ext = hi - lo;
             S[r] = ext > 0.0 ? ext : 1.0;
         }
-        // c^ = S^-1 (c - M n) with M n = m x n: the scaled blocks are
-        //   S^-1 (Acc - Acn M^T - M Acn^T + M Ann M^T) S^-1,  S^-1 (Acn - M Ann),  Ann
-        // and the right-hand side -S^-1 (sum c e - M sum n e), -sum n e
         const double M[9] = {0.0, -m[2], m[1], m[2], 0.0, -m[0], -m[1], m[0], 0.0};
-        double Acc[9], Acn[9], Ann[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) {
-                Acc[3 * r + c] = A[6 * r + c];
-                Acn[3 * r + c] = A[6 * r + 3 + c];
-                Ann[3 * r + c] = A[6 * (r + 3) + 3 + c];
-            }
-        double MAnn[9], AcnMt[9], Bcn[9], Bcc[9];
+        double MAnn[9], AcnMt[9];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
                 double s1 = 0.0, s2 = 0.0;
                 for (int l = 0; l < 3; ++l) {
-                    s1 += M[3 * r + l] * Ann[3 * l + c];
-                    s2 += Acn[3 * r + l] * M[3 * c + l];
+                    s1 += M[3 * r + l] * A[6 * (l + 3) + 3 + c];    // M Ann
+                    s2 += A[6 * r + 3 + l] * M[3 * c + l];          // Acn M^T
                 }
                 MAnn[3 * r + c] = s1;
                 AcnMt[3 * r + c] = s2;
             }
+        double Bcc[9], Bcn[9], bc[3];
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
                 double mam = 0.0;
                 for (int l = 0; l < 3; ++l) mam += MAnn[3 * r + l] * M[3 * c + l];   // M Ann M^T
-                Bcc[3 * r + c] = (Acc[3 * r + c] - AcnMt[3 * r + c] - AcnMt[3 * c + r] + mam) / (S[r] * S[c]);
-                Bcn[3 * r + c] = (Acn[3 * r + c] - MAnn[3 * r + c]) / S[r];
+                Bcc[3 * r + c] = (A[6 * r + c] - AcnMt[3 * r + c] - AcnMt[3 * c + r] + mam) / (S[r] * S[c]);
+                Bcn[3 * r + c] = (A[6 * r + 3 + c] - MAnn[3 * r + c]) / S[r];
             }
-        double bc[3];
         for (int r = 0; r < 3; ++r) {
             double mb = 0.0;
             for (int l = 0; l < 3; ++l) mb += M[3 * r + l] * v[24 + l];
@@ -274,38 +355,53 @@ __global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__
             }
         }
     }
-    for (int q = 0; q < 36; ++q) res->C[q] = A[q];
-    for (int q = 0; q < 6; ++q) res->b[q] = b[q];
+    for (int q = 0; q < 36; ++q) sys.A[q] = A[q];
+    for (int q = 0; q < 6; ++q) sys.b[q] = b[q];
     for (int q = 0; q < 3; ++q) {
-        res->m[q] = m[q];
-        res->S[q] = S[q];
+        sys.m[q] = m[q];
+        sys.S[q] = S[q];
     }
-    res->residual2 = v[27];
-    res->pairs = (int64_t)N;
+    sys.N = N;
+    sys.e2 = v[27];
+}
 
+// Thresholded solution from the eigen-decomposition (V columns, lam), back-
+// substitution, and the pose update; writes the result record.
+__device__ void solve_and_update(const IcpSystem &sys, const double *V, const double *lam_in, const IcpArgs &a,
+                                 const double *pose, tsdf_icp_result *res)
+{
+    const double N = sys.N;
+    for (int q = 0; q < 36; ++q) res->C[q] = sys.A[q];
+    for (int q = 0; q < 6; ++q) res->b[q] = sys.b[q];
+    for (int q = 0; q < 3; ++q) {
+        res->m[q] = sys.m[q];
+        res->S[q] = sys.S[q];
+    }
+    res->residual2 = sys.e2;
+    res->pairs = (int64_t)N;
     double P[12];
     for (int q = 0; q < 12; ++q) P[q] = pose[q];
     double x[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, lam[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int kept = 0;
     if (N > 0.0) {
-        double Vec[36];
-        jacobi6(A, Vec, lam);
+        for (int e = 0; e < 6; ++e) lam[e] = lam_in[e];
         double xh[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int e = 0; e < 6; ++e) {
             const bool keep = lam[e] > 0.0 && (a.theta >= 0.0 ? lam[e] / N > a.theta : true);
             if (!keep) continue;
             ++kept;
             double vb = 0.0;
-            for (int r = 0; r < 6; ++r) vb += Vec[6 * r + e] * b[r];
-            for (int r = 0; r < 6; ++r) xh[r] += Vec[6 * r + e] * (vb / lam[e]);
+            for (int r = 0; r < 6; ++r) vb += V[6 * r + e] * sys.b[r];
+            for (int r = 0; r < 6; ++r) xh[r] += V[6 * r + e] * (vb / lam[e]);
         }
         // back to the unscaled increment: r = S^-1 r^, t = t^ - r x m
+        const double *S = sys.S, *m = sys.m;
         const double rr[3] = {xh[0] / S[0], xh[1] / S[1], xh[2] / S[2]};
         const double rxm[3] = {rr[1] * m[2] - rr[2] * m[1], rr[2] * m[0] - rr[0] * m[2], rr[0] * m[1] - rr[1] * m[0]};
-        x[0] = rr[0];
-        x[1] = rr[1];
-        x[2] = rr[2];
-        for (int q = 0; q < 3; ++q) x[3 + q] = xh[3 + q] - rxm[q];
+        for (int q = 0; q < 3; ++q) {
+            x[q] = rr[q];
+            x[3 + q] = xh[3 + q] - rxm[q];
+        }
         // R_inc = Rz(gamma) Ry(beta) Rx(alpha); pose' = R_inc pose + t_inc
         double sa, ca, sb, cb, sg, cg;
         sincos(x[0], &sa, &ca);
@@ -355,6 +451,30 @@ __global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__
     res->pad = 0;
 }
 
+__global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__restrict__ partial, int groups,
+                                                                const double *__restrict__ pose, IcpArgs a,
+                                                                tsdf_icp_result *__restrict__ res)
+{
+    __shared__ ReduceLds L;
+    __shared__ IcpSystem sys;
+    __shared__ double sV[36], sLam[6];
+    double v[32], bx[8];
+    init_acc(v, bx);
+#pragma unroll 4
+    for (int g = threadIdx.x; g < groups; g += kIcpThreads) {
+#pragma unroll
+        for (int k = 0; k < 32; ++k) v[k] += partial[(size_t)k * groups + g];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bx[k] = fmax(bx[k], partial[(size_t)(32 + k) * groups + g]);
+    }
+    block_reduce(v, bx, L);
+    if (threadIdx.x == 0) system_of(L.tot, a, sys);
+    __syncthreads();
+    if (threadIdx.x < 64 && sys.N > 0.0) jacobi6_wave(sys.A, sV, sLam);
+    __syncthreads();
+    if (threadIdx.x == 0) solve_and_update(sys, sV, sLam, a, pose, res);
+}
+
 int icp_groups(int32_t width, int32_t height)
 {
     const long long npix = (long long)width * height;
@@ -386,7 +506,7 @@ extern "C" {
 uint64_t tsdf_icp_workspace_bytes(int32_t width, int32_t height)
 {
     if (width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
-    return (uint64_t)icp_groups(width, height) * kStride * sizeof(double);
+    return (uint64_t)icp_groups(width, height) * kPartial * sizeof(double);
 }
 
 tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
