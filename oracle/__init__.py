@@ -25,6 +25,8 @@ _SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c")]
 
 HIT, AMBIGUOUS, BISECT_INVALID, MARGINAL = 1, 2, 4, 8
 NOISE_QUADRATIC, NOISE_CONSTANT, NOISE_PER_PIXEL = 0, 1, 2
+RULE_KALMAN, RULE_RUNNING, RULE_WEIGHTED = 0, 1, 2       # Algorithms 3, 1 and 2
+WEIGHT_CONSTANT, WEIGHT_INV_VARIANCE = 0, 1
 CHI = 2.0
 
 
@@ -75,6 +77,8 @@ def lib():
         for name in ("orc_alg1_step",):
             getattr(L, name).argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.orc_alg2_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_set_rule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        L.orc_set_rule.restype = ctypes.c_int
         L.orc_mlp_param_count.restype = ctypes.c_int
         L.orc_bf16.restype = ctypes.c_double
         L.orc_bf16.argtypes = [ctypes.c_double]
@@ -126,6 +130,12 @@ class OracleVolume:
     @property
     def n_blocks(self) -> int:
         return int(lib().orc_block_count(self.h))
+
+    def set_rule(self, rule: int, weight_kind: int = WEIGHT_CONSTANT, w: float = 1.0, w_max: float = math.inf):
+        """Update algorithm of later integrations (RULE_KALMAN, RULE_RUNNING, RULE_WEIGHTED)."""
+        rc = lib().orc_set_rule(self.h, int(rule), int(weight_kind), float(w), float(w_max))
+        if rc != 0:
+            raise ValueError(f"oracle set_rule failed with status {rc}")
 
     def integrate(self, depth, K, pose, noise_kind: int = NOISE_QUADRATIC, coeff: float = 0.0015,
                   phat: Optional[np.ndarray] = None) -> dict:

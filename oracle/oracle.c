@@ -29,6 +29,9 @@ struct orc_volume {
     double origin[3];    /* min corner of the grid */
     double delta;        /* truncation distance, metres */
     double q_hat;        /* process variance Q / delta^2 */
+    int32_t rule;        /* ORC_RULE_*: which update algorithm fuses measurements */
+    int32_t weight_kind; /* ORC_WEIGHT_*: w_k of Algorithms 1 and 2 */
+    double w, w_max;     /* constant weight; cap of the weight sum (Algorithm 2) */
     int32_t *offset;     /* N0*N1*N2 entries: block index or -1 */
     int32_t *keys;       /* cap*3 block coordinates, allocation order */
     double *T, *P;       /* cap*512 each */
@@ -74,6 +77,10 @@ orc_volume *orc_create(const int32_t dims[3], double voxel_size, const double or
     v->vs = voxel_size;
     v->delta = trunc_voxels * voxel_size;
     v->q_hat = q_hat;
+    v->rule = ORC_RULE_KALMAN;
+    v->weight_kind = ORC_WEIGHT_CONSTANT;
+    v->w = 1.0;
+    v->w_max = INFINITY;
     v->cap = capacity_blocks;
     v->offset = (int32_t *)malloc(sizeof(int32_t) * nb);
     for (int64_t b = 0; b < nb; ++b) v->offset[b] = -1;
@@ -176,6 +183,22 @@ static int measure(const orc_volume *v, const camera *c, const float *depth, int
     *pj = j;
     *ps = s;
     return 1;
+}
+
+/* Update algorithm of the volume's later integrations (see oracle.h). */
+int orc_set_rule(orc_volume *v, int32_t rule, int32_t weight_kind, double w, double w_max)
+{
+    if (!v || rule < ORC_RULE_KALMAN || rule > ORC_RULE_WEIGHTED) return ORC_EINVAL;
+    if (weight_kind != ORC_WEIGHT_CONSTANT && weight_kind != ORC_WEIGHT_INV_VARIANCE) return ORC_EINVAL;
+    if (rule == ORC_RULE_RUNNING && (weight_kind != ORC_WEIGHT_CONSTANT || !(w > 0.0 && w <= 1.0))) return ORC_EINVAL;
+    if (rule == ORC_RULE_WEIGHTED && weight_kind == ORC_WEIGHT_CONSTANT && !(w > 0.0 && isfinite(w)))
+        return ORC_EINVAL;
+    if (rule == ORC_RULE_WEIGHTED && !(w_max > 0.0)) return ORC_EINVAL;
+    v->rule = rule;
+    v->weight_kind = weight_kind;
+    v->w = w;
+    v->w_max = w_max;
+    return ORC_OK;
 }
 
 /* Algorithm 1 (plain running update), normalised units. */
@@ -308,7 +331,15 @@ int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const
                             break;
                         }
                         int64_t k = b * BVOX + (gx % BLOCK) + BLOCK * (gy % BLOCK) + BLOCK * BLOCK * (gz % BLOCK);
-                        orc_alg3_step(&v->T[k], &v->P[k], sd / v->delta, pk, v->q_hat);
+                        if (v->rule == ORC_RULE_RUNNING) {
+                            orc_alg1_step(&v->T[k], sd / v->delta, v->w);
+                        } else if (v->rule == ORC_RULE_WEIGHTED) {
+                            /* the weight sum W lives in P's place */
+                            double wk = v->weight_kind == ORC_WEIGHT_INV_VARIANCE ? 1.0 / pk : v->w;
+                            orc_alg2_step(&v->T[k], &v->P[k], sd / v->delta, wk, v->w_max);
+                        } else {
+                            orc_alg3_step(&v->T[k], &v->P[k], sd / v->delta, pk, v->q_hat);
+                        }
                         s.updates++;
                     }
         }

@@ -78,6 +78,15 @@ void orc_mlp_forward(const double *params, const double *x, int64_t n, double *s
 double orc_mlp_loss_grad(const double *params, const double *x, const double *r, int64_t n, double *grad,
                          int32_t round_bf16);
 
+/* Update algorithm of later integrations.  KALMAN: Algorithm 3 (state T,
+ * variance P).  RUNNING: Algorithm 1, T <- (1 - w) T + w T_k with constant
+ * w in (0, 1]; P is not used.  WEIGHTED: Algorithm 2 with w_k = w (CONSTANT)
+ * or w_k = 1 / p_k (INV_VARIANCE, the measurement variance in delta^2 units)
+ * and the weight sum W, capped at w_max, stored in P's place. */
+enum { ORC_RULE_KALMAN = 0, ORC_RULE_RUNNING = 1, ORC_RULE_WEIGHTED = 2 };
+enum { ORC_WEIGHT_CONSTANT = 0, ORC_WEIGHT_INV_VARIANCE = 1 };
+int orc_set_rule(orc_volume *v, int32_t rule, int32_t weight_kind, double w, double w_max);
+
 /* Scalar update rules (normalised units, chi = any |T| > 1). */
 void orc_alg1_step(double *T, double Tk, double w);
 void orc_alg2_step(double *T, double *Wsum, double Tk, double w, double w_max);
