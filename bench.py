@@ -77,13 +77,16 @@ def fuse_bytes(st, elem, pixels):
     return (4 * elem * upd_old + 2 * 512 * elem * st["total_new_blocks"] + 8 * pixels + 4 * st["total_candidates"])
 
 
-def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=None):
+def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=None, rule=None):
     """noise: None (quadratic) or bf16 MLP parameters (learned variance).
-    frames: pre-generated (depths, poses) to reuse."""
+    frames: pre-generated (depths, poses) to reuse.
+    rule: None (Algorithm 3) or (rule, weight_kind, w, w_max) for tsdf_set_update_rule."""
     from paper_1311_7194_amd import Volume
 
     K = spec.K
     vol = Volume.from_grid(spec.grid, storage=storage, q_hat=q_hat, max_width=K.width, max_height=K.height)
+    if rule is not None:
+        vol.set_update_rule(*rule)
     log(f"{spec.name}: volume {vol.nbytes / 2**30:.2f} GiB, generating {steps} frames")
     depths, poses = frames if frames is not None else generate(spec, max(steps, warmup))
     kind = 0 if noise is None else 2
@@ -423,6 +426,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="also run the 16-scene batched workload")
     ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
     ap.add_argument("--icp", type=int, default=1, help="also time point-to-plane ICP on the fused volume")
+    ap.add_argument("--rules", type=int, default=1, help="also run the orbit with Algorithms 1 and 2")
     ap.add_argument("--icp-iters", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -488,6 +492,17 @@ def main():
                          "updates_per_frame": rl["updates"] // rl["frames"]})
         log(json.dumps({k: v for k, v in rl.items() if not k.startswith("_")}))
         del rl
+    if args.rules:
+        # Algorithms 1 and 2 on the same frames (the same candidates and decisions, another update)
+        for name, rule in (("alg1-running w=0.1", (1, 0, 0.1, math.inf)),
+                           ("alg2-weighted w=1 cap 64", (2, 0, 1.0, 64.0))):
+            rr = run_sequence(spec, storage, args.steps, args.warmup, frames=res["_frames"], rule=rule)
+            variants.append({"workload": rr["workload"], "update_rule": name, "storage": rr["storage"],
+                             "frames": rr["frames"], "voxel_updates_per_s": round(rr["voxel_updates_per_s"], 1),
+                             "fuse_us_per_frame": round(rr["fuse_avg_us"], 2),
+                             "updates_per_frame": rr["updates"] // rr["frames"]})
+            log(json.dumps({k: v for k, v in rr.items() if not k.startswith("_")}))
+            del rr
     if args.icp:
         ri = run_icp(res, spec, iters=args.icp_iters)
         log(json.dumps(ri))

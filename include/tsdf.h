@@ -91,6 +91,18 @@ typedef enum {
     TSDF_NOISE_MLP = 2         /* learned per-pixel variance, quadratic fallback (tsdf_mlp.h) */
 } tsdf_noise_kind;
 
+/* Update algorithm that fuses measurements (tsdf_set_update_rule). */
+typedef enum {
+    TSDF_RULE_KALMAN = 0,      /* Algorithm 3: state T, variance P (default) */
+    TSDF_RULE_RUNNING = 1,     /* Algorithm 1: T <- (1 - w) T + w T_k, constant w in (0, 1]; P unused (0) */
+    TSDF_RULE_WEIGHTED = 2     /* Algorithm 2: weighted mean, weight sum W capped at w_max, stored in P */
+} tsdf_update_rule;
+
+typedef enum {
+    TSDF_WEIGHT_CONSTANT = 0,      /* w_k = w */
+    TSDF_WEIGHT_INV_VARIANCE = 1   /* w_k = 1 / p_hat_k, the measurement variance of the noise model */
+} tsdf_weight_kind;
+
 typedef struct {
     int32_t kind;              /* tsdf_noise_kind */
     double coeff;              /* see tsdf_noise_kind; the MLP uses it for its fallback */
@@ -101,7 +113,7 @@ typedef struct {
     uint64_t allocated_blocks;    /* blocks in the pool */
     uint64_t frame_candidates;    /* candidate blocks examined by the last integrate */
     uint64_t frame_new_blocks;    /* blocks allocated by the last integrate */
-    uint64_t frame_updates;       /* Algorithm 3 executions in the last integrate */
+    uint64_t frame_updates;       /* voxel updates (update-rule executions) in the last integrate */
     uint64_t frame_fresh_updates; /* ... of which in blocks that frame allocated */
     uint64_t total_updates;       /* totals since creation or reset */
     uint64_t total_fresh_updates;
@@ -166,6 +178,19 @@ tsdf_status tsdf_raycast(tsdf_volume *vol, const tsdf_intrinsics *K, const doubl
 tsdf_status tsdf_raycast_footprint(tsdf_volume *vol, const tsdf_intrinsics *K, const double pose_c2w[12],
                                    float *vertex_dev, float *normal_dev, uint64_t *blocks_out,
                                    hipStream_t stream);
+
+/* Update algorithm of later integrations (Section 7.1): Algorithm 3 (the
+ * default), Algorithm 1 with constant weight w in (0, 1] (weight_kind must be
+ * TSDF_WEIGHT_CONSTANT), or Algorithm 2 with w_k = w > 0 or w_k = 1 / p_hat_k
+ * and the weight sum capped at w_max > 0 (may be +Inf with FP32 storage; at
+ * most 65504 with FP16 storage, where stored weights are clamped to 65504).
+ * Allocation does not depend on the rule.  P holds the Kalman variance, 0
+ * (Algorithm 1) or the weight sum W (Algorithm 2): switching rules on a
+ * volume that holds data reinterprets it, so set the rule after creation or
+ * tsdf_reset_volume (which keeps it).  With inverse-variance weights and no
+ * cap, Algorithm 2 is Algorithm 3 with Q = 0 (P = 1/W).  Host-side: takes
+ * effect for calls enqueued afterwards.  TSDF_EINVAL for other values. */
+tsdf_status tsdf_set_update_rule(tsdf_volume *vol, int32_t rule, int32_t weight_kind, double w, double w_max);
 
 /* Lanes that march one ray together in the raycast (1, 2, 4, 8 or 16; default 8).
  * Every group size gives bitwise the same maps; only the speed differs. */

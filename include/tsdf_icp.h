@@ -37,7 +37,8 @@
  * maps are read once.  The paper reads the reduced system back and solves on
  * the CPU; here the 6x6 eigen-decomposition (cyclic Jacobi, double
  * precision) runs on the device and nothing is synchronised.  Successive
- * iterations chain by passing a result's pose as the next call's pose.
+ * iterations chain by passing a result's pose as the next call's pose, or
+ * all at once through tsdf_icp_run.
  *
  * Conventions are those of tsdf.h.
  */
@@ -95,6 +96,17 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
                           const float *model_normal_dev, const double model_pose_c2w[12], const double *pose_dev,
                           const tsdf_icp_params *params, void *workspace_dev, uint64_t workspace_bytes,
                           tsdf_icp_result *result_dev, hipStream_t stream);
+
+/* `iters` chained iterations (1..1024) from the host pose pose_init_c2w (12
+ * doubles, read during the call): iteration 0 starts from it, iteration k
+ * from results_dev[k - 1].pose.  results_dev holds `iters` records (device).
+ * Enqueues 2 * iters kernels and no copy; same errors as tsdf_icp_step, and
+ * TSDF_EINVAL for a non-finite initial pose or iters out of range. */
+tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                         const float *model_normal_dev, const double model_pose_c2w[12],
+                         const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,
+                         void *workspace_dev, uint64_t workspace_bytes, tsdf_icp_result *results_dev,
+                         hipStream_t stream);
 
 #ifdef __cplusplus
 }

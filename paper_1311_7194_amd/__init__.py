@@ -6,5 +6,6 @@ device tensors.
 """
 
 from .tsdf import (  # noqa: F401
-    F16, F32, NOISE_CONSTANT, NOISE_MLP, NOISE_QUADRATIC, Batch, Icp, TsdfError, Volume, lib, LIB_PATH,
+    F16, F32, NOISE_CONSTANT, NOISE_MLP, NOISE_QUADRATIC, RULE_KALMAN, RULE_RUNNING, RULE_WEIGHTED,
+    WEIGHT_CONSTANT, WEIGHT_INV_VARIANCE, Batch, Icp, TsdfError, Volume, lib, LIB_PATH,
 )

@@ -300,6 +300,52 @@ __device__ __forceinline__ void kalman(float &T, float &P, float Tk, float pk, f
     if (fabsf(T) > 1.0f) T = kChi;
 }
 
+// Algorithm 1: T <- (1 - w) T + w T_k, evaluated as T + w (T_k - T) (a first
+// measurement sets T = T_k).  The fused forms are written out so that every
+// kernel that inlines these rules rounds them the same way.
+__device__ __forceinline__ void running_mean(float &T, float Tk, float w)
+{
+    T = fabsf(T) > 1.0f ? Tk : fmaf(w, Tk - T, T);
+    if (fabsf(T) > 1.0f) T = kChi;
+}
+
+// Algorithm 2: the weighted mean with weight sum W (kept in P's place),
+// capped at w_max; a first measurement sets T = T_k, W = w_k.
+__device__ __forceinline__ void weighted_mean(float &T, float &W, float Tk, float wk, float w_max)
+{
+    if (fabsf(T) > 1.0f) {
+        T = Tk;
+        W = wk;
+    } else {
+        T = fmaf(W, T, wk * Tk) * __builtin_amdgcn_rcpf(W + wk);
+        W = fminf(W + wk, w_max);
+    }
+    if (fabsf(T) > 1.0f) T = kChi;
+}
+
+// The volume's update rule on one voxel with a measurement (the rule is a
+// template argument so that each rule's loop is compiled on its own).
+template <int kRule>
+__device__ __forceinline__ void update_voxel(const VolumeView &v, float &T, float &P, float Tk, float pk)
+{
+    if constexpr (kRule == TSDF_RULE_KALMAN) {
+        kalman(T, P, Tk, pk, v.q_hat);
+    } else if constexpr (kRule == TSDF_RULE_RUNNING) {
+        running_mean(T, Tk, v.w);
+    } else {
+        weighted_mean(T, P, Tk, v.weight_kind == TSDF_WEIGHT_INV_VARIANCE ? __builtin_amdgcn_rcpf(pk) : v.w,
+                      v.w_max);
+    }
+}
+
+// What P holds after a voxel's first measurement under the volume's rule.
+__device__ __forceinline__ float first_p(const VolumeView &v, float pk)
+{
+    if (v.rule == TSDF_RULE_KALMAN) return pk;
+    if (v.rule == TSDF_RULE_RUNNING) return 0.0f;
+    return v.weight_kind == TSDF_WEIGHT_INV_VARIANCE ? __builtin_amdgcn_rcpf(pk) : v.w;
+}
+
 template <typename S>
 __device__ __forceinline__ float load_s(const S *p);
 template <>
@@ -323,6 +369,15 @@ __device__ __forceinline__ float stored_value<__half>(float x) { return __half2f
 
 // Workgroups (of four wavefronts) of the persistent fusion grid.
 constexpr uint32_t kFuseGrid = 2560;
+
+// P as it goes to storage: FP16 cannot hold an Algorithm 2 weight sum above
+// 65504, so it is clamped there (variances never come near it).
+template <typename S>
+__device__ __forceinline__ float stored_weight(float p);
+template <>
+__device__ __forceinline__ float stored_weight<float>(float p) { return p; }
+template <>
+__device__ __forceinline__ float stored_weight<__half>(float p) { return fminf(p, 65504.0f); }
 
 // Event counts a wavefront accumulates over the candidates it processes.
 struct FuseAcc {
@@ -460,7 +515,7 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
         for (int z = 0; z < 8; ++z) {
             const bool m = (vmask >> z) & 1u;
             store_s(bt + 64 * z, m ? Tk[z] : kChi);
-            store_s(bp + 64 * z, m ? pk[z] : 0.0f);
+            store_s(bp + 64 * z, m ? stored_weight<S>(first_p(v, pk[z])) : 0.0f);
             if (m) kmin = min(kmin, order_key(stored_value<S>(Tk[z])));
         }
         live = vmask;
@@ -478,18 +533,27 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
                 P[z] = load_s(bp + 64 * z);
             }
         }
+        auto update = [&](auto rule) {
+            constexpr int kRule = decltype(rule)::value;
 #pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            if ((vmask >> z) & 1u) {
-                kalman(T[z], P[z], Tk[z], pk[z], v.q_hat);
-                store_s(bt + 64 * z, T[z]);
-                store_s(bp + 64 * z, P[z]);
-                if (fabsf(T[z]) <= 1.0f) {
-                    kmin = min(kmin, order_key(stored_value<S>(T[z])));
-                    live |= 1u << z;
+            for (int z = 0; z < 8; ++z) {
+                if ((vmask >> z) & 1u) {
+                    update_voxel<kRule>(v, T[z], P[z], Tk[z], pk[z]);
+                    store_s(bt + 64 * z, T[z]);
+                    store_s(bp + 64 * z, stored_weight<S>(P[z]));
+                    if (fabsf(T[z]) <= 1.0f) {
+                        kmin = min(kmin, order_key(stored_value<S>(T[z])));
+                        live |= 1u << z;
+                    }
                 }
             }
-        }
+        };
+        if (v.rule == TSDF_RULE_KALMAN)
+            update(std::integral_constant<int, TSDF_RULE_KALMAN>());
+        else if (v.rule == TSDF_RULE_RUNNING)
+            update(std::integral_constant<int, TSDF_RULE_RUNNING>());
+        else
+            update(std::integral_constant<int, TSDF_RULE_WEIGHTED>());
     }
     // the owner wavefront folds its new values into the bound (values only
     // ever lower it, so it stays below the true minimum)

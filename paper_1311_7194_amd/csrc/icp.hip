@@ -41,7 +41,15 @@ struct IcpArgs {
     double cos2;               // cos_min^2
     double theta;
     int32_t shrink;
+    double P0[12];             // current pose when the kernels get no device pose
 };
+
+// The current pose estimate: the device record or, for a chain's first
+// iteration, the host pose passed in the kernel arguments.
+__device__ __forceinline__ double pose_at(const double *pose, const IcpArgs &a, int q)
+{
+    return pose ? pose[q] : a.P0[q];
+}
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && isfinite(d); }
 
@@ -113,8 +121,8 @@ __global__ __launch_bounds__(kIcpThreads) void icp_pairs_kernel(const float *__r
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Rc[3 * r + c] = pose[4 * r + c];
-        tc[r] = pose[4 * r + 3];
+        for (int c = 0; c < 3; ++c) Rc[3 * r + c] = pose_at(pose, a, 4 * r + c);
+        tc[r] = pose_at(pose, a, 4 * r + 3);
     }
     double v[32], bx[8];
     init_acc(v, bx);
@@ -380,7 +388,7 @@ __device__ void solve_and_update(const IcpSystem &sys, const double *V, const do
     res->residual2 = sys.e2;
     res->pairs = (int64_t)N;
     double P[12];
-    for (int q = 0; q < 12; ++q) P[q] = pose[q];
+    for (int q = 0; q < 12; ++q) P[q] = pose_at(pose, a, q);
     double x[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, lam[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int kept = 0;
     if (N > 0.0) {
@@ -509,12 +517,16 @@ uint64_t tsdf_icp_workspace_bytes(int32_t width, int32_t height)
     return (uint64_t)icp_groups(width, height) * kPartial * sizeof(double);
 }
 
-tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
-                          const float *model_normal_dev, const double model_pose_c2w[12], const double *pose_dev,
-                          const tsdf_icp_params *params, void *workspace_dev, uint64_t workspace_bytes,
-                          tsdf_icp_result *result_dev, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// Validates the arguments shared by tsdf_icp_step and tsdf_icp_run and fills the kernel arguments.
+tsdf_status icp_args(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                     const float *model_normal_dev, const double *model_pose_c2w, const tsdf_icp_params *params,
+                     void *workspace_dev, uint64_t workspace_bytes, const void *result_dev, IcpArgs &a)
 {
-    if (!depth_dev || !K || !model_vertex_dev || !model_normal_dev || !model_pose_c2w || !pose_dev || !params ||
+    if (!depth_dev || !K || !model_vertex_dev || !model_normal_dev || !model_pose_c2w || !params ||
         !workspace_dev || !result_dev)
         return TSDF_EINVAL;
     if (!(isfinite(K->fx) && isfinite(K->fy) && isfinite(K->cx) && isfinite(K->cy) && K->fx > 0 && K->fy > 0))
@@ -526,7 +538,6 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
         !(isfinite(params->cos_min) && params->cos_min >= -1.0 && params->cos_min <= 1.0) ||
         !isfinite(params->theta) || (params->shrink != 0 && params->shrink != 1))
         return TSDF_EINVAL;
-    IcpArgs a;
     for (int r = 0; r < 3; ++r) {
         for (int c = 0; c < 3; ++c) a.Rm[3 * r + c] = model_pose_c2w[4 * r + c];
         a.tm[r] = model_pose_c2w[4 * r + 3];
@@ -541,12 +552,56 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
     a.cos2 = params->cos_min * params->cos_min;
     a.theta = params->theta;
     a.shrink = params->shrink;
-    const int groups = icp_groups(K->width, K->height);
+    for (int q = 0; q < 12; ++q) a.P0[q] = 0.0;
+    return TSDF_OK;
+}
+
+void icp_enqueue(const float *depth_dev, const float *mv, const float *mn, const double *pose_dev, const IcpArgs &a,
+                 void *workspace_dev, tsdf_icp_result *result_dev, hipStream_t stream)
+{
+    const int groups = icp_groups(a.width, a.height);
     double *partial = (double *)workspace_dev;
-    hipLaunchKernelGGL(icp_pairs_kernel, dim3(groups), dim3(kIcpThreads), 0, stream, depth_dev,
-                       (const float4 *)model_vertex_dev, (const float4 *)model_normal_dev, pose_dev, a, partial);
+    hipLaunchKernelGGL(icp_pairs_kernel, dim3(groups), dim3(kIcpThreads), 0, stream, depth_dev, (const float4 *)mv,
+                       (const float4 *)mn, pose_dev, a, partial);
     hipLaunchKernelGGL(icp_solve_kernel, dim3(1), dim3(kIcpThreads), 0, stream, partial, groups, pose_dev, a,
                        result_dev);
+}
+
+}  // namespace
+
+extern "C" {
+
+tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                          const float *model_normal_dev, const double model_pose_c2w[12], const double *pose_dev,
+                          const tsdf_icp_params *params, void *workspace_dev, uint64_t workspace_bytes,
+                          tsdf_icp_result *result_dev, hipStream_t stream)
+{
+    IcpArgs a;
+    if (!pose_dev) return TSDF_EINVAL;
+    const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
+                                    workspace_dev, workspace_bytes, result_dev, a);
+    if (st != TSDF_OK) return st;
+    icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, pose_dev, a, workspace_dev, result_dev, stream);
+    return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
+}
+
+tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                         const float *model_normal_dev, const double model_pose_c2w[12],
+                         const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,
+                         void *workspace_dev, uint64_t workspace_bytes, tsdf_icp_result *results_dev,
+                         hipStream_t stream)
+{
+    IcpArgs a;
+    if (!pose_init_c2w || iters < 1 || iters > 1024) return TSDF_EINVAL;
+    for (int q = 0; q < 12; ++q)
+        if (!isfinite(pose_init_c2w[q])) return TSDF_EINVAL;
+    const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
+                                    workspace_dev, workspace_bytes, results_dev, a);
+    if (st != TSDF_OK) return st;
+    for (int q = 0; q < 12; ++q) a.P0[q] = pose_init_c2w[q];
+    for (int k = 0; k < iters; ++k)
+        icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, k == 0 ? nullptr : results_dev[k - 1].pose, a,
+                    workspace_dev, results_dev + k, stream);
     return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
 }
 

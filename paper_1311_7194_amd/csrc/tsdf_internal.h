@@ -66,6 +66,9 @@ struct VolumeView {
     double origin[3];
     double delta, inv_delta;
     float q_hat;
+    int32_t rule;               // tsdf_update_rule
+    int32_t weight_kind;        // tsdf_weight_kind
+    float w, w_max;             // Algorithms 1 and 2: constant weight, cap of the weight sum
     uint32_t capacity;
     uint32_t hash_mask;
     uint32_t max_candidates;

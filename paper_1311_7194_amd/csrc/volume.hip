@@ -419,6 +419,10 @@ tsdf_status tsdf_create_volume(const tsdf_volume_desc *desc, void *dev_buf, uint
     w.delta = desc->trunc_voxels * desc->voxel_size;
     w.inv_delta = 1.0 / w.delta;
     w.q_hat = (float)desc->q_hat;
+    w.rule = TSDF_RULE_KALMAN;
+    w.weight_kind = TSDF_WEIGHT_CONSTANT;
+    w.w = 1.0f;
+    w.w_max = INFINITY;
     w.capacity = desc->capacity_blocks;
     w.hash_mask = desc->hash_slots - 1;
     w.max_candidates = v->desc.max_candidates;
@@ -441,6 +445,26 @@ void tsdf_destroy_volume(tsdf_volume *vol)
     }
     for (hipEvent_t e : vol->spare) hipEventDestroy(e);
     delete vol;
+}
+
+tsdf_status tsdf_set_update_rule(tsdf_volume *vol, int32_t rule, int32_t weight_kind, double w, double w_max)
+{
+    if (!vol) return TSDF_EINVAL;
+    if (rule != TSDF_RULE_KALMAN && rule != TSDF_RULE_RUNNING && rule != TSDF_RULE_WEIGHTED) return TSDF_EINVAL;
+    if (weight_kind != TSDF_WEIGHT_CONSTANT && weight_kind != TSDF_WEIGHT_INV_VARIANCE) return TSDF_EINVAL;
+    if (rule == TSDF_RULE_RUNNING && (weight_kind != TSDF_WEIGHT_CONSTANT || !(w > 0.0 && w <= 1.0)))
+        return TSDF_EINVAL;
+    if (rule == TSDF_RULE_WEIGHTED) {
+        if (weight_kind == TSDF_WEIGHT_CONSTANT && !(w > 0.0 && w <= 3.0e38)) return TSDF_EINVAL;
+        if (!(w_max > 0.0)) return TSDF_EINVAL;
+        if (vol->desc.storage == TSDF_F16 && !(w_max <= 65504.0)) return TSDF_EINVAL;
+    }
+    vol->view.rule = rule;
+    vol->view.weight_kind = weight_kind;
+    vol->view.w = (float)w;
+    vol->view.w_max = (float)fmin(w_max, 3.0e38);
+    if (isinf(w_max)) vol->view.w_max = INFINITY;
+    return TSDF_OK;
 }
 
 tsdf_status tsdf_reset_volume(tsdf_volume *vol, hipStream_t stream)

@@ -9,6 +9,7 @@ fails loudly otherwise - there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Sequence
 
@@ -20,6 +21,8 @@ LIB_PATH = os.path.join(HERE, "libtsdf.so")
 
 F32, F16 = 0, 1
 NOISE_QUADRATIC, NOISE_CONSTANT, NOISE_MLP = 0, 1, 2
+RULE_KALMAN, RULE_RUNNING, RULE_WEIGHTED = 0, 1, 2          # Algorithms 3, 1 and 2 (tsdf_update_rule)
+WEIGHT_CONSTANT, WEIGHT_INV_VARIANCE = 0, 1
 FLAG_POOL_FULL, FLAG_HASH_FULL, FLAG_CAND_FULL = 1, 2, 4
 OK, EINVAL, ENOMEM, EFULL, EHIP, ESTATE = 0, 1, 2, 3, 4, 5
 
@@ -30,7 +33,8 @@ EXPORTED = [
     "tsdf_set_raycast_group", "tsdf_get_raycast_group", "tsdf_autotune_raycast", "tsdf_raycast_footprint",
     "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
-    "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step",
+    "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step", "tsdf_icp_run",
+    "tsdf_set_update_rule",
 ]
 
 
@@ -104,6 +108,7 @@ def lib():
         L.tsdf_import_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P]
         L.tsdf_set_timing.argtypes = [P, ctypes.c_int32]
         L.tsdf_set_raycast_group.argtypes = [P, ctypes.c_int32]
+        L.tsdf_set_update_rule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         L.tsdf_get_raycast_group.argtypes = [P]
         L.tsdf_autotune_raycast.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P]
         L.tsdf_read_timing.argtypes = [P, P, ctypes.c_int32]
@@ -122,6 +127,7 @@ def lib():
         L.tsdf_icp_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
         L.tsdf_icp_workspace_bytes.restype = ctypes.c_uint64
         L.tsdf_icp_step.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_uint64, P, P]
+        L.tsdf_icp_run.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint64, P, P]
         for name in EXPORTED:
             if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy",
                             "tsdf_icp_workspace_bytes"):
@@ -255,6 +261,12 @@ class Volume:
         st = Stats()
         _check(lib().tsdf_query_stats(self.handle, ctypes.byref(st)), "tsdf_query_stats")
         return st.as_dict()
+
+    def set_update_rule(self, rule: int, weight_kind: int = WEIGHT_CONSTANT, w: float = 1.0,
+                        w_max: float = math.inf):
+        """Algorithm 3 (RULE_KALMAN, default), 1 (RULE_RUNNING) or 2 (RULE_WEIGHTED) for later integrations."""
+        _check(lib().tsdf_set_update_rule(self.handle, int(rule), int(weight_kind), float(w), float(w_max)),
+               "tsdf_set_update_rule")
 
     def set_raycast_group(self, group: int):
         _check(lib().tsdf_set_raycast_group(self.handle, int(group)), "tsdf_set_raycast_group")
@@ -429,7 +441,6 @@ class Icp:
             raise TsdfError(EINVAL, "tsdf_icp_workspace_bytes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.results = torch.zeros((max_iters, ICP_RESULT_DOUBLES), dtype=torch.float64, device=device)
-        self.pose0 = torch.zeros(12, dtype=torch.float64, device=device)
 
     def step(self, depth: torch.Tensor, model_vertex: torch.Tensor, model_normal: torch.Tensor, model_pose,
              pose_dev: torch.Tensor, k: int = 0, stream=None) -> torch.Tensor:
@@ -448,11 +459,13 @@ class Icp:
         device pose after the last one (record iters - 1)."""
         if not 1 <= iters <= self.results.shape[0]:
             raise ValueError("iters")
-        self.pose0.copy_(torch.as_tensor(_pose_array(pose)))
-        cur = self.pose0
-        for k in range(iters):
-            cur = self.step(depth, model_vertex, model_normal, model_pose, cur, k, stream)
-        return cur
+        mp, p0 = _pose_array(model_pose), _pose_array(pose)
+        _check(lib().tsdf_icp_run(_ptr(depth), ctypes.byref(self.K), _ptr(model_vertex), _ptr(model_normal),
+                                  mp.ctypes.data_as(ctypes.c_void_p), p0.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(self.params), int(iters), _ptr(self.workspace),
+                                  ctypes.c_uint64(self.workspace.numel()), _ptr(self.results),
+                                  stream_handle(stream)), "tsdf_icp_run")
+        return self.results[iters - 1, :12]
 
     def result(self, k: int = 0) -> dict:
         """Record k as a dict (synchronises)."""

@@ -143,3 +143,20 @@ def test_icp_host_validation(lib):
                 T.IcpParams(0.02, 1.5, 0.005, 1, 0), T.IcpParams(0.02, 0.9, float("inf"), 1, 0),
                 T.IcpParams(0.02, 0.9, 0.005, 2, 0)):
         assert call(params=bad) == T.EINVAL
+
+
+def test_update_rule_validation_without_volume(lib):
+    assert lib.tsdf_set_update_rule(None, 0, 0, 1.0, 1.0) == T.EINVAL
+
+
+def test_icp_run_host_validation(lib):
+    K = T.Intrinsics(525.0, 525.0, 319.5, 239.5, 640, 480)
+    eye = (ctypes.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    bad = (ctypes.c_double * 12)(float("nan"), 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    prm = T.IcpParams(0.02, 0.9, 0.005, 1, 0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+    ws = ctypes.c_uint64(lib.tsdf_icp_workspace_bytes(640, 480))
+    run = lambda pose, iters, res=fake: lib.tsdf_icp_run(fake, ctypes.byref(K), fake, fake, eye, pose,  # noqa: E731
+                                                         ctypes.byref(prm), iters, fake, ws, res, None)
+    assert run(eye, 0) == T.EINVAL and run(eye, 1025) == T.EINVAL
+    assert run(bad, 1) == T.EINVAL and run(None, 1) == T.EINVAL and run(eye, 1, None) == T.EINVAL

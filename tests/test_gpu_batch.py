@@ -47,13 +47,18 @@ STAT_KEYS = ("allocated_blocks", "total_updates", "total_fresh_updates", "total_
              "total_candidates", "total_touched_blocks", "frames", "status_flags")
 
 
-@pytest.mark.parametrize("noise,graph,storage,dense,group", [
-    ("quadratic", True, 0, True, 4),
-    ("constant", False, 0, False, 8),
-    ("quadratic", True, 1, True, 1),
-    ("mlp", True, 0, True, 16),
+RULES = {0: {}, 1: dict(w=0.2), 2: dict(weight_kind=1, w_max=60000.0)}   # Algorithms 3, 1, 2
+
+
+@pytest.mark.parametrize("noise,graph,storage,dense,group,rule", [
+    ("quadratic", True, 0, True, 4, 0),
+    ("constant", False, 0, False, 8, 0),
+    ("quadratic", True, 1, True, 1, 0),
+    ("mlp", True, 0, True, 16, 0),
+    ("quadratic", True, 0, True, 4, 1),
+    ("quadratic", False, 1, True, 8, 2),
 ])
-def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group):
+def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group, rule):
     specs = scenes()
     kind = dict(quadratic=tsdf.NOISE_QUADRATIC, constant=tsdf.NOISE_CONSTANT, mlp=tsdf.NOISE_MLP)[noise]
     coeff = 0.05 if noise == "constant" else 0.0015
@@ -62,7 +67,11 @@ def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group):
         from paper_1311_7194_amd import mlp as M
 
         params = M.params_from_values(M.init_params(3))
-    mk = lambda s: gpu_volume_for(s, storage=storage, dense_index=dense)
+    def mk(s):
+        v = gpu_volume_for(s, storage=storage, dense_index=dense)
+        v.set_update_rule(rule, **RULES[rule])
+        return v
+
     batched = [mk(s) for s in specs]
     plain = [mk(s) for s in specs]
     b = tsdf.Batch(batched, [s.K for s in specs], graph=graph)
@@ -71,7 +80,8 @@ def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group):
         v.set_raycast_group(group)
     steps = max(s.n_frames for s in specs)
     for t in range(steps):
-        print(f"[batch] {noise} graph={graph} storage={storage} dense={dense} G={group} step {t}", flush=True)
+        print(f"[batch] {noise} graph={graph} storage={storage} dense={dense} G={group} rule={rule} step {t}",
+              flush=True)
         depths, poses = [], []
         for s in specs:
             if t < s.n_frames:
