@@ -78,6 +78,8 @@ def lib():
             getattr(L, name).argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.orc_alg2_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_set_rule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        L.orc_evict.argtypes = [P, P, P, P, P, P, ctypes.c_int64]
+        L.orc_evict.restype = ctypes.c_int64
         L.orc_set_rule.restype = ctypes.c_int
         L.orc_mlp_param_count.restype = ctypes.c_int
         L.orc_bf16.restype = ctypes.c_double
@@ -183,6 +185,18 @@ class OracleVolume:
         P = np.zeros((n, 512))
         lib().orc_export(self.h, _ptr(keys), _ptr(T), _ptr(P), n)
         return keys, T, P
+
+    def evict(self, lo, hi):
+        """Remove the blocks outside the block box [lo, hi]; returns their keys [n,3], T, P [n,512]."""
+        lo_, hi_ = np.ascontiguousarray(np.asarray(lo, np.int32)), np.ascontiguousarray(np.asarray(hi, np.int32))
+        cap = self.n_blocks
+        keys = np.zeros((max(cap, 1), 3), np.int32)
+        T = np.zeros((max(cap, 1), 512))
+        P = np.zeros((max(cap, 1), 512))
+        n = lib().orc_evict(self.h, _ptr(lo_), _ptr(hi_), _ptr(keys), _ptr(T), _ptr(P), cap)
+        if n < 0:
+            raise RuntimeError("oracle evict failed")
+        return keys[:n], T[:n], P[:n]
 
     def set_block(self, key, T, P=None):
         k = np.ascontiguousarray(np.asarray(key, np.int32))

@@ -513,6 +513,47 @@ int64_t orc_export(const orc_volume *v, int32_t *keys, double *T, double *P, int
     return v->n_blocks;
 }
 
+/* Eviction (future work in Section 8: stream out the blocks that leave the
+ * working volume): every block whose coordinates lie outside [lo, hi]
+ * (inclusive, per axis) is copied out, in allocation order, and removed;
+ * the remaining blocks keep their order and the offset table is rebuilt.
+ * Returns the number of blocks evicted, or -1 (nothing done) when more than
+ * cap would be. */
+int64_t orc_evict(orc_volume *v, const int32_t lo[3], const int32_t hi[3], int32_t *keys_out, double *T_out,
+                  double *P_out, int64_t cap)
+{
+    int64_t n_out = 0;
+    for (int64_t b = 0; b < v->n_blocks; ++b) {
+        int inside = 1;
+        for (int a = 0; a < 3; ++a) inside &= v->keys[3 * b + a] >= lo[a] && v->keys[3 * b + a] <= hi[a];
+        n_out += !inside;
+    }
+    if (n_out > cap) return -1;
+    int64_t kept = 0, e = 0;
+    for (int64_t b = 0; b < v->n_blocks; ++b) {
+        int inside = 1;
+        for (int a = 0; a < 3; ++a) inside &= v->keys[3 * b + a] >= lo[a] && v->keys[3 * b + a] <= hi[a];
+        v->offset[table_index(v, v->keys[3 * b], v->keys[3 * b + 1], v->keys[3 * b + 2])] = -1;
+        if (!inside) {
+            memcpy(keys_out + 3 * e, v->keys + 3 * b, sizeof(int32_t) * 3);
+            memcpy(T_out + BVOX * e, v->T + BVOX * b, sizeof(double) * BVOX);
+            memcpy(P_out + BVOX * e, v->P + BVOX * b, sizeof(double) * BVOX);
+            ++e;
+            continue;
+        }
+        if (kept != b) {
+            memcpy(v->keys + 3 * kept, v->keys + 3 * b, sizeof(int32_t) * 3);
+            memmove(v->T + BVOX * kept, v->T + BVOX * b, sizeof(double) * BVOX);
+            memmove(v->P + BVOX * kept, v->P + BVOX * b, sizeof(double) * BVOX);
+        }
+        ++kept;
+    }
+    v->n_blocks = kept;
+    for (int64_t b = 0; b < kept; ++b)
+        v->offset[table_index(v, v->keys[3 * b], v->keys[3 * b + 1], v->keys[3 * b + 2])] = (int32_t)b;
+    return e;
+}
+
 int orc_set_block(orc_volume *v, const int32_t key[3], const double *T, const double *P)
 {
     for (int a = 0; a < 3; ++a)

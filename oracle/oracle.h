@@ -66,6 +66,11 @@ int orc_sample(const orc_volume *v, const double p[3], double *F);
 /* Block store access, in allocation order: keys n*3 (block coordinates),
  * T and P n*512 in voxel order x + 8y + 64z. */
 int64_t orc_export(const orc_volume *v, int32_t *keys, double *T, double *P, int64_t cap);
+/* Remove every block outside the block-coordinate box [lo, hi] (inclusive),
+ * copying it out first (keys_out n*3, T_out and P_out n*512, allocation
+ * order); the others keep their order.  Returns n, or -1 if n > cap. */
+int64_t orc_evict(orc_volume *v, const int32_t lo[3], const int32_t hi[3], int32_t *keys_out, double *T_out,
+                  double *P_out, int64_t cap);
 /* Allocate (if needed) block (bx, by, bz) and overwrite its 512 voxels. */
 int orc_set_block(orc_volume *v, const int32_t key[3], const double *T, const double *P);
 
