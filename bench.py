@@ -142,6 +142,24 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
     return res
 
 
+def run_evict(res):
+    """Block eviction on the fused volume: the blocks of the half-grid x >= G/2
+    are streamed out and the rest compacted (two host syncs included)."""
+    vol = res["_vol"]
+    n0 = int(vol.stats()["allocated_blocks"])
+    nb = vol.desc.dims[0] // 8
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keys, T, P = vol.evict([0, 0, 0], [nb // 2 - 1, 1023, 1023])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    n = int(keys.shape[0])
+    moved = 2 * n * 512 * T.element_size()
+    return {"workload": res["workload"], "stage": "evict", "allocated_blocks": n0, "evicted_blocks": n,
+            "kept_blocks": n0 - n, "ms": round(ms, 3), "evicted_blocks_per_s": round(n / (ms * 1e-3), 1),
+            "evicted_gb_per_s": round(moved / (ms * 1e-3) / 1e9, 2)}
+
+
 ICP_BYTES_PER_PIXEL = 36   # live depth (4 B) + one model vertex and normal (2 x 16 B) per pixel
 
 
@@ -427,6 +445,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
     ap.add_argument("--icp", type=int, default=1, help="also time point-to-plane ICP on the fused volume")
     ap.add_argument("--rules", type=int, default=1, help="also run the orbit with Algorithms 1 and 2")
+    ap.add_argument("--evict", type=int, default=1, help="also time block eviction on the fused volume")
     ap.add_argument("--icp-iters", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -507,6 +526,10 @@ def main():
         ri = run_icp(res, spec, iters=args.icp_iters)
         log(json.dumps(ri))
         variants.append(ri)
+    if args.evict:
+        re_ = run_evict(res)
+        log(json.dumps(re_))
+        variants.append(re_)
     if args.variants and args.config != "c3":
         spec3 = make_spec("c3", args.variant_steps)
         r32 = run_sequence(spec3, 0, args.variant_steps, 3)

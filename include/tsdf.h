@@ -222,6 +222,24 @@ tsdf_status tsdf_read_timing(tsdf_volume *vol, tsdf_timing *out, int32_t reset);
 tsdf_status tsdf_export_blocks(tsdf_volume *vol, int32_t *keys_dev, void *T_dev, void *P_dev,
                                uint64_t cap, uint64_t *n_out, hipStream_t stream);
 
+/* Device workspace of tsdf_evict_blocks for this volume (0 for null). */
+uint64_t tsdf_evict_workspace_bytes(const tsdf_volume *vol);
+
+/* Block eviction, the volume shift named as future work in Section 8: every
+ * allocated block whose block coordinates lie outside [lo, hi] (inclusive,
+ * per axis; host arrays) is copied out and removed.  keys_dev int32 [cap][3],
+ * T_dev and P_dev [cap][512] of the storage type receive the evicted blocks,
+ * in no particular order; *n_out (host) their number.  The kept blocks move
+ * to the front of the pool, and the hash table, occupancy bits and dense
+ * index are rebuilt from them; their values are unchanged.  A later frame
+ * that reaches an evicted block allocates it afresh; tsdf_import_blocks
+ * streams evicted blocks back in.  Synchronises `stream` twice.  Returns
+ * TSDF_ENOMEM, changing nothing, when more than cap blocks would be evicted
+ * (*n_out is then the number needed); TSDF_EFULL as tsdf_integrate_frame. */
+tsdf_status tsdf_evict_blocks(tsdf_volume *vol, const int32_t lo[3], const int32_t hi[3], int32_t *keys_dev,
+                              void *T_dev, void *P_dev, uint64_t cap, void *work_dev, uint64_t work_bytes,
+                              uint64_t *n_out, hipStream_t stream);
+
 /* Insert (or overwrite) n blocks: keys_dev int32 [n][3] distinct block
  * coordinates inside the grid, T_dev/P_dev [n][512] of the storage type. */
 tsdf_status tsdf_import_blocks(tsdf_volume *vol, const int32_t *keys_dev, const void *T_dev,

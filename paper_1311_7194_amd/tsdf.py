@@ -34,7 +34,7 @@ EXPORTED = [
     "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
     "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step", "tsdf_icp_run",
-    "tsdf_set_update_rule",
+    "tsdf_set_update_rule", "tsdf_evict_workspace_bytes", "tsdf_evict_blocks",
 ]
 
 
@@ -108,6 +108,9 @@ def lib():
         L.tsdf_import_blocks.argtypes = [P, P, P, P, ctypes.c_uint64, P]
         L.tsdf_set_timing.argtypes = [P, ctypes.c_int32]
         L.tsdf_set_raycast_group.argtypes = [P, ctypes.c_int32]
+        L.tsdf_evict_workspace_bytes.argtypes = [P]
+        L.tsdf_evict_workspace_bytes.restype = ctypes.c_uint64
+        L.tsdf_evict_blocks.argtypes = [P, P, P, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P, P]
         L.tsdf_set_update_rule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         L.tsdf_get_raycast_group.argtypes = [P]
         L.tsdf_autotune_raycast.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P]
@@ -130,7 +133,7 @@ def lib():
         L.tsdf_icp_run.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint64, P, P]
         for name in EXPORTED:
             if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy",
-                            "tsdf_icp_workspace_bytes"):
+                            "tsdf_icp_workspace_bytes", "tsdf_evict_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -309,6 +312,24 @@ class Volume:
         if m:
             _check(lib().tsdf_export_blocks(self.handle, _ptr(keys), _ptr(T), _ptr(P), m, ctypes.byref(n),
                                             stream_handle(stream)), "tsdf_export_blocks")
+        return keys[:m], T[:m], P[:m]
+
+    def evict(self, lo, hi, stream=None):
+        """Remove the blocks outside the block-coordinate box [lo, hi] and
+        return them as (keys [n,3] int32, T, P [n,512]) device tensors."""
+        cap = max(int(self.stats()["allocated_blocks"]), 1)
+        dev = self.buffer.device
+        keys = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        T = torch.empty((cap, 512), dtype=self.elem_dtype, device=dev)
+        P = torch.empty_like(T)
+        work = torch.empty(int(lib().tsdf_evict_workspace_bytes(self.handle)), dtype=torch.uint8, device=dev)
+        lo_ = (ctypes.c_int32 * 3)(*[int(x) for x in lo])
+        hi_ = (ctypes.c_int32 * 3)(*[int(x) for x in hi])
+        n = ctypes.c_uint64(0)
+        _check(lib().tsdf_evict_blocks(self.handle, lo_, hi_, _ptr(keys), _ptr(T), _ptr(P), ctypes.c_uint64(cap),
+                                       _ptr(work), ctypes.c_uint64(work.numel()), ctypes.byref(n),
+                                       stream_handle(stream)), "tsdf_evict_blocks")
+        m = int(n.value)
         return keys[:m], T[:m], P[:m]
 
     def import_blocks(self, keys: torch.Tensor, T: torch.Tensor, P: torch.Tensor, stream=None):
