@@ -3,7 +3,7 @@
 //
 //   count    evicted blocks among the allocated slots (the call returns
 //            TSDF_ENOMEM before changing anything if they do not fit)
-//   mark     one wavefront per slot: an evicted block is copied out; an
+//   mark     one lane per slot: an evicted block is copied out; an
 //            evicted slot below the new block count K is a hole, a kept slot
 //            at or above K is a mover (there are as many of each)
 //   move     one wavefront per mover: its voxels, key, bound and box go to a
@@ -41,6 +41,10 @@ __global__ __launch_bounds__(256) void evict_count_kernel(VolumeView v, uint32_t
     }
 }
 
+// One wavefront per 64 consecutive slots: each lane classifies one slot, the
+// wavefront reserves its ranges of the output, hole and mover lists with one
+// atomic each, then copies its evicted blocks one after the other (64 lanes
+// per block, coalesced).
 template <typename S>
 __global__ __launch_bounds__(256) void evict_mark_kernel(VolumeView v, uint32_t n, uint32_t K, int3 lo, int3 hi,
                                                          int32_t *__restrict__ keys_out, S *__restrict__ T_out,
@@ -48,34 +52,48 @@ __global__ __launch_bounds__(256) void evict_mark_kernel(VolumeView v, uint32_t 
                                                          uint32_t *__restrict__ movers, EvictCounters *c)
 {
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const uint32_t nw = gridDim.x * 4u;
-    for (uint32_t s = blockIdx.x * 4u + (threadIdx.x >> 6); s < n; s += nw) {
-        const uint32_t key = v.pool_keys[s];
-        const bool out = !inside_box(key, lo, hi);
-        uint32_t e = 0;
+    for (uint32_t base = (blockIdx.x * 4u + (threadIdx.x >> 6)) * 64u; base < n; base += nw * 64u) {
+        const uint32_t s = base + lane;
+        const bool valid = s < n;
+        const uint32_t key = valid ? v.pool_keys[s] : 0u;
+        const bool out = valid && !inside_box(key, lo, hi);
+        const bool hole = out && s < K, mover = valid && !out && s >= K;
+        const unsigned long long mo = __ballot(out), mh = __ballot(hole), mm = __ballot(mover);
+        uint32_t e0 = 0, h0 = 0, m0 = 0;
         if (lane == 0) {
-            if (out) {
-                e = atomicAdd(&c->exported, 1u);
-                if (s < K) holes[atomicAdd(&c->holes, 1u)] = s;
-            } else if (s >= K) {
-                movers[atomicAdd(&c->movers, 1u)] = s;
-            }
+            if (mo) e0 = atomicAdd(&c->exported, (uint32_t)__popcll(mo));
+            if (mh) h0 = atomicAdd(&c->holes, (uint32_t)__popcll(mh));
+            if (mm) m0 = atomicAdd(&c->movers, (uint32_t)__popcll(mm));
         }
-        if (!out) continue;
-        e = __shfl(e, 0);
-        const S *srcT = (const S *)v.poolT + (size_t)s * kBlockVoxels;
-        const S *srcP = (const S *)v.poolP + (size_t)s * kBlockVoxels;
-        S *dT = T_out + (size_t)e * kBlockVoxels;
-        S *dP = P_out + (size_t)e * kBlockVoxels;
-#pragma unroll
-        for (int q = 0; q < kBlockVoxels / 64; ++q) {
-            dT[q * 64 + lane] = srcT[q * 64 + lane];
-            dP[q * 64 + lane] = srcP[q * 64 + lane];
-        }
-        if (lane < 3) {
+        e0 = __shfl(e0, 0);
+        h0 = __shfl(h0, 0);
+        m0 = __shfl(m0, 0);
+        if (hole) holes[h0 + __popcll(mh & below)] = s;
+        if (mover) movers[m0 + __popcll(mm & below)] = s;
+        if (out) {
+            const uint32_t e = e0 + (uint32_t)__popcll(mo & below);
             int b[3];
             unpack_key(key, b[0], b[1], b[2]);
-            keys_out[3 * (size_t)e + lane] = b[lane];
+            keys_out[3 * (size_t)e + 0] = b[0];
+            keys_out[3 * (size_t)e + 1] = b[1];
+            keys_out[3 * (size_t)e + 2] = b[2];
+        }
+        unsigned long long rest = mo;
+        for (uint32_t r = 0; rest; ++r) {
+            const int l = __ffsll((long long)rest) - 1;
+            rest &= rest - 1ull;
+            const uint32_t src = base + (uint32_t)l, dst = e0 + r;
+            const S *srcT = (const S *)v.poolT + (size_t)src * kBlockVoxels;
+            const S *srcP = (const S *)v.poolP + (size_t)src * kBlockVoxels;
+            S *dT = T_out + (size_t)dst * kBlockVoxels;
+            S *dP = P_out + (size_t)dst * kBlockVoxels;
+#pragma unroll
+            for (int q = 0; q < kBlockVoxels / 64; ++q) {
+                dT[q * 64 + lane] = srcT[q * 64 + lane];
+                dP[q * 64 + lane] = srcP[q * 64 + lane];
+            }
         }
     }
 }
