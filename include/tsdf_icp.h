@@ -74,8 +74,9 @@ typedef struct {
     int32_t pad;
 } tsdf_icp_result;
 
-/* Device workspace that tsdf_icp_step needs for a width x height depth map
- * (0 if a dimension is outside 1..16384). */
+/* Device workspace that tsdf_icp_step and tsdf_icp_run need for a width x
+ * height depth map (0 if a dimension is outside 1..16384): per-workgroup
+ * partial sums and the last iteration's eigenvectors. */
 uint64_t tsdf_icp_workspace_bytes(int32_t width, int32_t height);
 
 /* One iteration.
@@ -100,8 +101,12 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
 /* `iters` chained iterations (1..1024) from the host pose pose_init_c2w (12
  * doubles, read during the call): iteration 0 starts from it, iteration k
  * from results_dev[k - 1].pose.  results_dev holds `iters` records (device).
- * Enqueues 2 * iters kernels and no copy; same errors as tsdf_icp_step, and
- * TSDF_EINVAL for a non-finite initial pose or iters out of range. */
+ * Enqueues 2 * iters kernels and no copy.  Iterations after the first start
+ * their eigen-decomposition from the previous iteration's eigenvectors (kept
+ * in the workspace), which the nearly unchanged system needs only a sweep or
+ * two to finish; the result is the same decomposition to rounding.  Same
+ * errors as tsdf_icp_step, and TSDF_EINVAL for a non-finite initial pose or
+ * iters out of range. */
 tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
                          const float *model_normal_dev, const double model_pose_c2w[12],
                          const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,

@@ -243,14 +243,17 @@ __device__ __forceinline__ void plane_rotation(double app, double aqq, double ap
     s = t * c;
 }
 
-// Called by the 64 lanes of one wavefront; sA (read) and sV, sLam (written) in LDS.
-__device__ void jacobi6_wave(const double *sA, double *sV, double *sLam)
+// Called by the 64 lanes of one wavefront; sA and sV0 (read) and sV, sLam
+// (written) in LDS.  sV0 is the rotation the sweeps start from: null for the
+// identity, or an orthogonal V0 when sA holds V0^T A V0, so that the
+// eigenvectors come out for A itself.
+__device__ void jacobi6_wave(const double *sA, const double *sV0, double *sV, double *sLam)
 {
     const int lane = threadIdx.x & 63;
     const bool own = lane < 36;
     const int r = own ? lane / 6 : 0, c = own ? lane % 6 : 0;
     double a = own ? sA[lane] : 0.0;
-    double v = own && r == c ? 1.0 : 0.0;
+    double v = own ? (sV0 ? sV0[lane] : (r == c ? 1.0 : 0.0)) : 0.0;
     for (int sweep = 0; sweep < 64; ++sweep) {
         double off = 0.0, diag = 0.0;
         for (int p = 0; p < 6; ++p) {
@@ -459,13 +462,19 @@ __device__ void solve_and_update(const IcpSystem &sys, const double *V, const do
     res->pad = 0;
 }
 
+// warm: start the eigen-decomposition from the previous iteration's
+// eigenvectors (kept in vwork): the system changes little from one iteration
+// to the next, so V^T A V is nearly diagonal and a sweep or two finish it.
 __global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__restrict__ partial, int groups,
                                                                 const double *__restrict__ pose, IcpArgs a,
-                                                                tsdf_icp_result *__restrict__ res)
+                                                                tsdf_icp_result *__restrict__ res,
+                                                                double *__restrict__ vwork, int warm)
 {
     __shared__ ReduceLds L;
     __shared__ IcpSystem sys;
-    __shared__ double sV[36], sLam[6];
+    __shared__ double sV[36], sLam[6], sV0[36], sB[36], sA2[36];
+    const int t = threadIdx.x;
+    if (warm && t < 36) sV0[t] = vwork[t];
     double v[32], bx[8];
     init_acc(v, bx);
 #pragma unroll 4
@@ -476,11 +485,30 @@ __global__ __launch_bounds__(kIcpThreads) void icp_solve_kernel(const double *__
         for (int k = 0; k < 8; ++k) bx[k] = fmax(bx[k], partial[(size_t)(32 + k) * groups + g]);
     }
     block_reduce(v, bx, L);
-    if (threadIdx.x == 0) system_of(L.tot, a, sys);
+    if (t == 0) system_of(L.tot, a, sys);
     __syncthreads();
-    if (threadIdx.x < 64 && sys.N > 0.0) jacobi6_wave(sys.A, sV, sLam);
+    const bool use_warm = warm && sys.N > 0.0;
+    if (use_warm) {   // sB = (V0^T A V0), symmetrised
+        const int r = t / 6, c = t % 6;
+        if (t < 36) {
+            double s = 0.0;
+            for (int l = 0; l < 6; ++l) s += sys.A[6 * r + l] * sV0[6 * l + c];
+            sB[t] = s;
+        }
+        __syncthreads();
+        if (t < 36) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += sV0[6 * k + r] * sB[6 * k + c];
+            sA2[t] = s;
+        }
+        __syncthreads();
+        if (t < 36) sB[t] = 0.5 * (sA2[t] + sA2[6 * c + r]);
+        __syncthreads();
+    }
+    if (t < 64 && sys.N > 0.0) jacobi6_wave(use_warm ? sB : sys.A, use_warm ? sV0 : nullptr, sV, sLam);
     __syncthreads();
-    if (threadIdx.x == 0) solve_and_update(sys, sV, sLam, a, pose, res);
+    if (t < 36) vwork[t] = sys.N > 0.0 ? sV[t] : (t % 7 == 0 ? 1.0 : 0.0);
+    if (t == 0) solve_and_update(sys, sV, sLam, a, pose, res);
 }
 
 int icp_groups(int32_t width, int32_t height)
@@ -514,7 +542,8 @@ extern "C" {
 uint64_t tsdf_icp_workspace_bytes(int32_t width, int32_t height)
 {
     if (width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
-    return (uint64_t)icp_groups(width, height) * kPartial * sizeof(double);
+    // partials, then the last eigenvectors (36 doubles) for a warm start
+    return (uint64_t)icp_groups(width, height) * kPartial * sizeof(double) + 36 * sizeof(double);
 }
 
 }  // extern "C"
@@ -557,14 +586,15 @@ tsdf_status icp_args(const float *depth_dev, const tsdf_intrinsics *K, const flo
 }
 
 void icp_enqueue(const float *depth_dev, const float *mv, const float *mn, const double *pose_dev, const IcpArgs &a,
-                 void *workspace_dev, tsdf_icp_result *result_dev, hipStream_t stream)
+                 void *workspace_dev, tsdf_icp_result *result_dev, int warm, hipStream_t stream)
 {
     const int groups = icp_groups(a.width, a.height);
     double *partial = (double *)workspace_dev;
+    double *vwork = partial + (size_t)groups * kPartial;
     hipLaunchKernelGGL(icp_pairs_kernel, dim3(groups), dim3(kIcpThreads), 0, stream, depth_dev, (const float4 *)mv,
                        (const float4 *)mn, pose_dev, a, partial);
     hipLaunchKernelGGL(icp_solve_kernel, dim3(1), dim3(kIcpThreads), 0, stream, partial, groups, pose_dev, a,
-                       result_dev);
+                       result_dev, vwork, warm);
 }
 
 }  // namespace
@@ -581,7 +611,7 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
     const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
                                     workspace_dev, workspace_bytes, result_dev, a);
     if (st != TSDF_OK) return st;
-    icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, pose_dev, a, workspace_dev, result_dev, stream);
+    icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, pose_dev, a, workspace_dev, result_dev, 0, stream);
     return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
 }
 
@@ -601,7 +631,7 @@ tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const
     for (int q = 0; q < 12; ++q) a.P0[q] = pose_init_c2w[q];
     for (int k = 0; k < iters; ++k)
         icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, k == 0 ? nullptr : results_dev[k - 1].pose, a,
-                    workspace_dev, results_dev + k, stream);
+                    workspace_dev, results_dev + k, k > 0, stream);
     return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
 }
 

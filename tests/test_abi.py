@@ -118,7 +118,7 @@ def test_icp_host_validation(lib):
     assert lib.tsdf_icp_workspace_bytes(0, 480) == 0
     assert lib.tsdf_icp_workspace_bytes(640, 16385) == 0
     ws = lib.tsdf_icp_workspace_bytes(640, 480)
-    assert ws == 512 * 40 * 8 and lib.tsdf_icp_workspace_bytes(16, 16) == 40 * 8
+    assert ws == 512 * 40 * 8 + 36 * 8 and lib.tsdf_icp_workspace_bytes(16, 16) == 40 * 8 + 36 * 8
     assert ctypes.sizeof(T.IcpResult) == 600 and ctypes.sizeof(T.IcpParams) == 32
     K = T.Intrinsics(525.0, 525.0, 319.5, 239.5, 640, 480)
     pose = (ctypes.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
