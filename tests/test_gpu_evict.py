@@ -124,3 +124,18 @@ def test_evict_everything_then_fuse(tsdf):
     a, b = gpu_blocks(vol), gpu_blocks(fresh)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_evict_edge_cases(tsdf):
+    spec = small_orbit(width=100, height=75, n_frames=1)
+    empty = gpu_volume_for(spec)
+    k, _, _ = empty.evict([0, 0, 0], [0, 0, 0])
+    assert len(k) == 0 and empty.stats()["allocated_blocks"] == 0
+    vol = gpu_volume_for(spec)
+    fuse(vol, spec, [0], True)
+    before = gpu_blocks(vol)
+    k, _, _ = vol.evict([0, 0, 0], [1023, 1023, 1023])          # the box holds every block
+    assert len(k) == 0
+    after = gpu_blocks(vol)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)

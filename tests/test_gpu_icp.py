@@ -147,3 +147,16 @@ def test_registration_against_raycast_maps(tsdf):
     after = np.abs(est[:, 3] - truth[:, 3]).max()
     print(f"[icp] orbit frame 10: translation error {before:.4g} -> {after:.4g} m", flush=True)
     assert after < 0.1 * before
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (2, 2), (17, 5), (257, 3)])
+def test_tiny_and_ragged_frames(tsdf, w, h):
+    # fewer pixels than one workgroup, a single row of workgroups, no pixel
+    # with both neighbours (1x1): the pair count and pose still match
+    K = Intrinsics(120.0 * max(w, h) / 96.0, 120.0 * max(w, h) / 96.0, (w - 1) / 2.0, (h - 1) / 2.0, w, h)
+    model_pose = look_at((0.3, 0.5, 0.4), (-0.3, 0.0, -0.4))
+    live_pose = perturbed(model_pose, [0.002, -0.001, 0.003], [0.002, 0.001, -0.002])
+    depth = sensor_depth(CORNER, K, live_pose, noise_seed=5)
+    MV, MN = render_model_maps(CORNER, K, model_pose)
+    g, o = run_one(tsdf, depth, K, MV, MN, model_pose, model_pose, O.IcpParams(dist_max=0.05, cos_min=0.8))
+    compare(g, o, f"{w}x{h}")

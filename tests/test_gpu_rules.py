@@ -80,3 +80,20 @@ def test_rule_validation(tsdf):
     with pytest.raises(tsdf.TsdfError):
         v16.set_update_rule(2, 0, 1.0, math.inf)       # FP16 cannot hold an uncapped weight sum
     v16.set_update_rule(2, 0, 1.0, 65504.0)
+
+
+@pytest.mark.parametrize("name,rule,kw", [("running fp16", oracle.RULE_RUNNING, dict(w=0.2)),
+                                          ("weighted fp16", oracle.RULE_WEIGHTED, dict(w=1.0, w_max=8.0))])
+def test_rule_fp16_against_oracle(tsdf, name, rule, kw):
+    # FP16 storage rounds T and W on every store: same block set, T within
+    # a few FP16 ulps of the oracle's (reported bound, not the FP32 gate)
+    spec = small_orbit(width=100, height=75, n_frames=4)
+    gv, ov = gpu_volume_for(spec, storage=1), oracle_volume_for(spec)
+    gv.set_update_rule(rule, **kw)
+    ov.set_rule(rule, **kw)
+    for k in range(spec.n_frames):
+        depth, pose = sequence_frame(spec, k)
+        ov.integrate(depth.numpy(), Kvec(spec.K), pose)
+        gv.integrate(depth.cuda(), spec.K, pose)
+    st = compare_volumes(gv, ov, t_tol=4e-3, p_rtol=4e-3)
+    print(f"[rules] {name}: {st}", flush=True)
