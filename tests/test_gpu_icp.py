@@ -160,3 +160,30 @@ def test_tiny_and_ragged_frames(tsdf, w, h):
     MV, MN = render_model_maps(CORNER, K, model_pose)
     g, o = run_one(tsdf, depth, K, MV, MN, model_pose, model_pose, O.IcpParams(dist_max=0.05, cos_min=0.8))
     compare(g, o, f"{w}x{h}")
+
+
+def test_tracking_loop_stays_on_the_true_trajectory(tsdf):
+    # fuse, raycast and register on the system's own estimates (frame 0 at its
+    # true pose) over 20 frames of the finely sampled orbit.  Directions the
+    # threshold drops are not corrected, so the estimate drifts slowly; it
+    # must stay far closer to the truth than the uncorrected trajectory (the
+    # previous pose reused), which is off by the whole motion
+    spec = config_c2(n_frames=1000)
+    K = spec.K
+    vol = tsdf.Volume.from_grid(spec.grid, max_width=K.width, max_height=K.height)
+    icp = tsdf.Icp(K, dist_max=0.05, cos_min=math.cos(math.radians(30.0)))
+    d0, est = sequence_frame(spec, 0)
+    vol.integrate(d0.cuda(), K, est)
+    worst = 0.0
+    for k in range(1, 20):
+        vert, nrm = vol.raycast(K, est)
+        depth, truth = sequence_frame(spec, k)
+        icp.run(depth.cuda(), vert, nrm, est, est, 10)
+        torch.cuda.synchronize()
+        est = icp.result(9)["pose"]
+        vol.integrate(depth.cuda(), K, est)
+        worst = max(worst, float(np.linalg.norm(est[:, 3] - truth[:, 3])))
+    uncorrected = float(np.linalg.norm(spec.poses[0][:, 3] - spec.poses[19][:, 3]))
+    print(f"[icp] tracking 20 frames: worst translation error {worst:.4g} m "
+          f"(uncorrected {uncorrected:.4g} m)", flush=True)
+    assert worst < 0.1 * uncorrected
