@@ -187,3 +187,27 @@ def test_tracking_loop_stays_on_the_true_trajectory(tsdf):
     print(f"[icp] tracking 20 frames: worst translation error {worst:.4g} m "
           f"(uncorrected {uncorrected:.4g} m)", flush=True)
     assert worst < 0.1 * uncorrected
+
+
+def test_step_chain_equals_run_chain(tsdf):
+    # tsdf_icp_step (cold eigen-decomposition every time, pose on the device)
+    # and tsdf_icp_run (warm start from the previous eigenvectors) give the
+    # same iterates to rounding
+    K = Intrinsics(240.0, 240.0, 95.5, 71.5, 192, 144)
+    true = look_at((0.3, 0.5, 0.4), (-0.3, 0.0, -0.4))
+    depth = sensor_depth(CORNER, K, true, noise_seed=21).cuda()
+    MV, MN = render_model_maps(CORNER, K, true)
+    MV, MN = MV.cuda(), MN.cuda()
+    start = perturbed(true, [0.01, -0.015, 0.012], [0.008, -0.006, 0.01])
+    a = tsdf.Icp(K, 0.05, 0.8)
+    b = tsdf.Icp(K, 0.05, 0.8)
+    a.run(depth, MV, MN, true, start, 6)
+    cur = torch.as_tensor(start.reshape(12)).cuda()
+    for k in range(6):
+        cur = b.step(depth, MV, MN, true, cur, k)
+    torch.cuda.synchronize()
+    for k in range(6):
+        ra, rb = a.result(k), b.result(k)
+        assert ra["N"] == rb["N"] and ra["kept"] == rb["kept"], k
+        assert np.abs(ra["pose"] - rb["pose"]).max() < 1e-10, k
+        assert np.abs(ra["lam"] - rb["lam"]).max() <= 1e-9 * np.abs(rb["lam"]).max(), k
