@@ -336,8 +336,6 @@ __device__ __forceinline__ bool sample_q(const VolumeView &v, SlotCache &cache, 
 }
 
 // First lattice index past the cell of block B along the ray (the caller's
-// samples before it all have their base voxel in B).
-// First lattice index past the cell of block B along the ray (the caller's
 // samples before it all have their base voxel in B).  The division by h is a
 // product with 1/h: the index found lies within one of the exit, and the
 // test of its sample then returns the exit or one index before it (a later
