@@ -6,7 +6,8 @@ scenes of the c5 batch through the batched step, each in the launch
 configuration the benchmark times (autotuned ray group, dense index).  The
 oracle integrates the same frames; whole volumes are compared (block sets
 bit-exact, values within tolerance) and the raycast is compared on a seeded
-sample of pixels that the oracle marches one by one.
+sample of pixels that the oracle marches one by one.  Algorithms 1 and 2 and
+the eviction are checked on the c2 volume the same way.
 """
 
 import numpy as np
@@ -86,3 +87,61 @@ def test_benchmark_size_batch(tsdf):
         rs = check_sampled_raycast(ov, b.vertex[i], b.normal[i], s.K, pose, s.grid.voxel_size, n=2000)
         print(f"[full] batch {s.name}", vs, rs, flush=True)
         assert rs["hits"] > 300
+
+
+@pytest.mark.parametrize("rule,kw", [(oracle.RULE_RUNNING, dict(w=0.2)),
+                                     (oracle.RULE_WEIGHTED, dict(w=1.0, w_max=8.0))], ids=["alg1", "alg2"])
+def test_benchmark_size_update_rules(tsdf, rule, kw):
+    """Algorithms 1 and 2 on the first two frames of the c2 orbit."""
+    spec = config_c2(n_frames=2)
+    K = spec.K
+    gv = tsdf.Volume.from_grid(spec.grid, max_width=K.width, max_height=K.height)
+    ov = oracle_volume_for(spec)
+    gv.set_update_rule(rule, **kw)
+    ov.set_rule(rule, **kw)
+    for k in range(2):
+        d, pose = sequence_frame(spec, k)
+        print(f"[full] rule {rule} frame {k}", flush=True)
+        ost = ov.integrate(d.numpy(), Kvec(K), pose)
+        gv.integrate(d.cuda(), K, pose)
+        st = gv.stats()
+        assert st["frame_updates"] == ost["updates"] and st["frame_new_blocks"] == ost["new_blocks"], (st, ost)
+    vs = compare_volumes(gv, ov)
+    print(f"[full] rule {rule}", vs, flush=True)
+    assert vs["live"] > 1000000
+
+
+def test_benchmark_size_eviction(tsdf):
+    """The eviction the benchmark times (blocks with x >= half the grid out)
+    after two frames of the c2 orbit, then a third frame fused into the
+    compacted volume."""
+    spec = config_c2(n_frames=3)
+    K = spec.K
+    gv = tsdf.Volume.from_grid(spec.grid, max_width=K.width, max_height=K.height)
+    ov = oracle_volume_for(spec)
+    for k in range(2):
+        d, pose = sequence_frame(spec, k)
+        ov.integrate(d.numpy(), Kvec(K), pose)
+        gv.integrate(d.cuda(), K, pose)
+    nb = spec.grid.dims[0] // 8
+    lo, hi = [0, 0, 0], [nb // 2 - 1, 1023, 1023]
+    gk, gT, gP = gv.evict(lo, hi)
+    ok_, oT, oP = ov.evict(lo, hi)
+    print(f"[full] eviction: gpu {len(gk)} / oracle {len(ok_)} blocks out", flush=True)
+    assert len(ok_) > 10000 and gv.stats()["allocated_blocks"] == ov.n_blocks > 10000
+    a = oracle.sorted_blocks(gk.cpu().numpy(), gT.float().cpu().numpy().astype(np.float64),
+                             gP.float().cpu().numpy().astype(np.float64))
+    b = oracle.sorted_blocks(ok_, oT, oP)
+    assert np.array_equal(a[0], b[0])
+    olive, glive = np.abs(b[1]) <= 1, np.abs(a[1]) <= 1
+    assert int((olive != glive).sum()) <= 1e-6 * olive.size      # the tolerance of compare_volumes
+    live = olive & glive
+    assert np.abs(a[1][live] - b[1][live]).max() <= 1e-5
+    assert (np.abs(a[2][live] - b[2][live]) <= 1e-5 * np.maximum(b[2][live], 1e-30)).all()
+    print("[full] kept", compare_volumes(gv, ov), flush=True)
+    d, pose = sequence_frame(spec, 2)
+    ost = ov.integrate(d.numpy(), Kvec(K), pose)
+    gv.integrate(d.cuda(), K, pose)
+    st = gv.stats()
+    assert st["frame_updates"] == ost["updates"] and st["frame_new_blocks"] == ost["new_blocks"], (st, ost)
+    print("[full] after a third frame", compare_volumes(gv, ov), flush=True)
