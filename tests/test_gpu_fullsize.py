@@ -7,7 +7,7 @@ configuration the benchmark times (autotuned ray group, dense index).  The
 oracle integrates the same frames; whole volumes are compared (block sets
 bit-exact, values within tolerance) and the raycast is compared on a seeded
 sample of pixels that the oracle marches one by one.  Algorithms 1 and 2 and
-the eviction are checked on the c2 volume the same way.
+the eviction are checked on the c2 volume the same way, FP16 storage on c3.
 """
 
 import numpy as np
@@ -16,7 +16,7 @@ import torch
 
 import oracle
 from synthetic.configs import config_c2, config_c3, config_c5, sequence_frame
-from tests.parity import Kvec, compare_raycast, compare_volumes, oracle_volume_for
+from tests.parity import Kvec, camera_depth, compare_raycast, compare_volumes, gpu_blocks, oracle_volume_for
 
 pytestmark = pytest.mark.gpu
 
@@ -145,3 +145,43 @@ def test_benchmark_size_eviction(tsdf):
     st = gv.stats()
     assert st["frame_updates"] == ost["updates"] and st["frame_new_blocks"] == ost["new_blocks"], (st, ost)
     print("[full] after a third frame", compare_volumes(gv, ov), flush=True)
+
+
+def test_benchmark_size_fp16(tsdf):
+    """FP16 storage on the first two frames of the c3 hand (4096^3, 1280x960),
+    with the bounds of the small FP16 case: block set and chi status exact,
+    T_hat within FP16 rounding, P_hat within 2 %, raycast depth within 0.1
+    voxel on the seeded pixels both sides hit."""
+    spec = config_c3(n_frames=2)
+    K = spec.K
+    gv = tsdf.Volume.from_grid(spec.grid, storage=tsdf.F16, max_width=K.width, max_height=K.height)
+    ov = oracle_volume_for(spec)
+    for k in range(2):
+        d, pose = sequence_frame(spec, k)
+        print(f"[full] fp16 {spec.name} frame {k}", flush=True)
+        ost = ov.integrate(d.numpy(), Kvec(K), pose)
+        gv.integrate(d.cuda(), K, pose)
+        st = gv.stats()
+        assert st["frame_updates"] == ost["updates"] and st["frame_new_blocks"] == ost["new_blocks"], (st, ost)
+    gk, gT, gP = gpu_blocks(gv)
+    ok_, oT, oP = oracle.sorted_blocks(*ov.export())
+    assert np.array_equal(gk, ok_)
+    glive, olive = np.abs(gT) <= 1, np.abs(oT) <= 1
+    assert np.array_equal(glive, olive)
+    dT = np.abs(gT[olive] - oT[olive])
+    rP = np.abs(gP[olive] - oP[olive]) / np.maximum(oP[olive], 1e-30)
+    print(f"[full] fp16 volume: live {int(olive.sum())}, max dT {dT.max():.3g}, rms dT "
+          f"{np.sqrt((dT ** 2).mean()):.3g}, max rel dP {rP.max():.3g}", flush=True)
+    assert dT.max() <= 2e-2 and np.sqrt((dT ** 2).mean()) <= 2e-3 and rP.max() <= 2e-2
+    vert, _ = gv.raycast(K, pose)
+    torch.cuda.synchronize()
+    pix = sample_pixels(K, 6000, 13)                  # the hand covers about 8 % of the frame
+    ovv, _, ofl = ov.raycast(Kvec(K), pose, K.width, K.height, pixels=pix, n_threads=8)
+    g = vert.cpu().numpy().reshape(-1, 4).astype(np.float64)[pix[:, 1] * K.width + pix[:, 0]]
+    ok = (ofl & (oracle.AMBIGUOUS | oracle.BISECT_INVALID | oracle.MARGINAL)) == 0
+    both = (g[:, 3] > 0) & ((ofl & oracle.HIT) > 0) & ok
+    mism = ((g[:, 3] > 0) != ((ofl & oracle.HIT) > 0)) & ok
+    dz = np.abs(camera_depth(g[both], pose) - camera_depth(ovv[both], pose)) / spec.grid.voxel_size
+    print(f"[full] fp16 raycast: {int(both.sum())} pixels, {int(mism.sum())} hit/miss differences, "
+          f"max dz {dz.max():.3g} voxel", flush=True)
+    assert both.sum() > 300 and mism.sum() <= 0.01 * len(pix) and dz.max() <= 0.1
