@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import oracle
-from synthetic.configs import config_c1, sequence_frame, small_orbit
+from synthetic.configs import config_c1, config_c2, sequence_frame, small_orbit
 from tests.parity import Kvec, compare_volumes, gpu_volume_for, oracle_volume_for
 
 pytestmark = pytest.mark.gpu
@@ -145,3 +145,23 @@ def test_integration_with_learned_variance(mlp):
         assert gst["frame_updates"] == ost["updates"]
     st = compare_volumes(gv, ov, t_tol=1e-2, p_rtol=5e-2)
     print("[mlp] learned-variance integration", st, flush=True)
+
+
+def test_integration_with_learned_variance_full_size(mlp):
+    """The same check on the first two frames of the 640x480 orbit into the
+    2048^3 grid, the configuration the benchmark's learned-noise line runs."""
+    spec = config_c2(n_frames=2)
+    p = trained_like_params(mlp, 8)
+    params = mlp.params_from_values(p)
+    gv = gpu_volume_for(spec)
+    ov = oracle_volume_for(spec)
+    for k in range(2):
+        d, pose = sequence_frame(spec, k)
+        ph = oracle.mlp_variance(d.numpy(), Kvec(spec.K), p, spec.grid.delta)
+        ost = ov.integrate(d.numpy(), Kvec(spec.K), pose, oracle.NOISE_PER_PIXEL, 0.0015, ph)
+        gv.integrate(d.cuda(), spec.K, pose, 2, 0.0015, params)
+        gst = gv.stats()
+        assert gst["frame_updates"] == ost["updates"] and gst["frame_new_blocks"] == ost["new_blocks"]
+    st = compare_volumes(gv, ov, t_tol=1e-2, p_rtol=5e-2)
+    print("[mlp] learned-variance integration, 640x480 orbit", st, flush=True)
+    assert st["live"] > 1000000
