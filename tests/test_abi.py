@@ -160,3 +160,13 @@ def test_icp_run_host_validation(lib):
                                                          ctypes.byref(prm), iters, fake, ws, res, None)
     assert run(eye, 0) == T.EINVAL and run(eye, 1025) == T.EINVAL
     assert run(bad, 1) == T.EINVAL and run(None, 1) == T.EINVAL and run(eye, 1, None) == T.EINVAL
+
+
+def test_evict_host_validation_without_volume(lib):
+    # a null volume is refused before anything touches a device
+    assert lib.tsdf_evict_workspace_bytes(None) == 0
+    lo = (ctypes.c_int32 * 3)(0, 0, 0)
+    n = ctypes.c_uint64(7)
+    work = ctypes.c_void_p(1 << 20)                     # never dereferenced: the call returns first
+    assert lib.tsdf_evict_blocks(None, lo, lo, None, None, None, 0, work, 1 << 20, ctypes.byref(n), None) == T.EINVAL
+    assert n.value == 7
