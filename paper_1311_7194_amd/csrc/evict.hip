@@ -195,7 +195,8 @@ tsdf_status tsdf_evict_blocks(tsdf_volume *vol, const int32_t lo[3], const int32
     hipLaunchKernelGGL(evict_fill_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)c, (uint64_t)64, 0u);
     hipLaunchKernelGGL(evict_count_kernel, dim3(kEvictGrid), dim3(256), 0, stream, v, n, blo, bhi, c);
     EvictCounters hc;
-    e = hipMemcpyAsync(&hc, c, sizeof(hc), hipMemcpyDeviceToHost, stream);
+    e = hipGetLastError();   // a failed launch leaves the counters unwritten: stop before reading them
+    if (e == hipSuccess) e = hipMemcpyAsync(&hc, c, sizeof(hc), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return TSDF_EHIP;
     const uint32_t E = hc.evicted;
