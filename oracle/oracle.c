@@ -201,47 +201,62 @@ int orc_set_rule(orc_volume *v, int32_t rule, int32_t weight_kind, double w, dou
     return ORC_OK;
 }
 
-/* Algorithm 1 (plain running update), normalised units. */
+/*
+ * The three update rules of Section 7.1 (Algorithms 1, 2 and 3), in
+ * normalised units.  All three move a voxel that already holds a value
+ * toward the measurement by a gain g in [0, 1],
+ *     T <- T + g (T_k - T),
+ * and differ only in g and in the second per-voxel quantity S they carry:
+ *   - Algorithm 1: g = w, a constant; S is not used.
+ *   - Algorithm 2: S is the weight sum W of Eq. (10).  The weighted mean
+ *     (W T + w_k T_k) / (W + w_k) is the increment with g = w_k / (W + w_k);
+ *     afterwards W becomes min(W + w_k, W_max).
+ *   - Algorithm 3: S is the variance P.  The prediction adds the process
+ *     variance, P' = P + Q; g is the Kalman gain P' / (P' + p_k) and the
+ *     variance becomes (1 - g) P'.
+ * A voxel without a value (chi) takes the measurement itself; S starts at
+ * the measurement's weight (Algorithm 2) or variance (Algorithm 3), with no
+ * prediction added.  A value that leaves [-1, 1] is chi again.  A chi
+ * measurement changes nothing.
+ */
+static void fuse_measurement(int rule, double *T, double *S, double Tk, double u, double q, double w_max)
+{
+    /* u: the constant weight w (Algorithm 1), the measurement's weight w_k
+     * (Algorithm 2) or its variance p_k (Algorithm 3) */
+    if (is_chi(Tk)) return;
+    if (is_chi(*T)) {
+        *T = Tk;
+        if (rule != ORC_RULE_RUNNING) *S = u;
+    } else {
+        double g;
+        if (rule == ORC_RULE_RUNNING) {
+            g = u;
+        } else if (rule == ORC_RULE_WEIGHTED) {
+            g = u / (*S + u);
+            *S = fmin(*S + u, w_max);
+        } else {
+            double pred = *S + q;
+            g = pred / (pred + u);
+            *S = (1.0 - g) * pred;
+        }
+        *T = *T + g * (Tk - *T);
+    }
+    if (is_chi(*T)) *T = CHI;
+}
+
 void orc_alg1_step(double *T, double Tk, double w)
 {
-    if (is_chi(Tk)) return;
-    if (is_chi(*T))
-        *T = Tk;
-    else
-        *T = (1.0 - w) * (*T) + w * Tk;
-    if (fabs(*T) > 1.0) *T = CHI;
+    fuse_measurement(ORC_RULE_RUNNING, T, NULL, Tk, w, 0.0, 0.0);
 }
 
-/* Algorithm 2 (weighted update with the weight sum of Eq. (10) capped at W_max). */
 void orc_alg2_step(double *T, double *Wsum, double Tk, double w, double w_max)
 {
-    if (is_chi(Tk)) return;
-    if (is_chi(*T)) {
-        *T = Tk;
-        *Wsum = w;
-    } else {
-        *T = ((*Wsum) * (*T) + w * Tk) / ((*Wsum) + w);
-        *Wsum = fmin((*Wsum) + w, w_max);
-    }
-    if (fabs(*T) > 1.0) *T = CHI;
+    fuse_measurement(ORC_RULE_WEIGHTED, T, Wsum, Tk, w, 0.0, w_max);
 }
 
-/* Algorithm 3 (Kalman filter): predict P += Q, gain K = P / (P + p_k),
- * correct T += K (T_k - T), P = (1 - K) P; a first measurement initialises
- * T = T_k, P = p_k. */
 void orc_alg3_step(double *T, double *P, double Tk, double pk, double q)
 {
-    if (is_chi(Tk)) return;
-    if (is_chi(*T)) {
-        *T = Tk;
-        *P = pk;
-    } else {
-        *P = *P + q;
-        double K = *P / (*P + pk);
-        *T = *T + K * (Tk - *T);
-        *P = (1.0 - K) * (*P);
-    }
-    if (fabs(*T) > 1.0) *T = CHI;
+    fuse_measurement(ORC_RULE_KALMAN, T, P, Tk, pk, q, 0.0);
 }
 
 /* Measurement variance in delta^2 units from the measured depth D.  The
@@ -331,15 +346,13 @@ int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const
                             break;
                         }
                         int64_t k = b * BVOX + (gx % BLOCK) + BLOCK * (gy % BLOCK) + BLOCK * BLOCK * (gz % BLOCK);
-                        if (v->rule == ORC_RULE_RUNNING) {
-                            orc_alg1_step(&v->T[k], sd / v->delta, v->w);
-                        } else if (v->rule == ORC_RULE_WEIGHTED) {
-                            /* the weight sum W lives in P's place */
-                            double wk = v->weight_kind == ORC_WEIGHT_INV_VARIANCE ? 1.0 / pk : v->w;
-                            orc_alg2_step(&v->T[k], &v->P[k], sd / v->delta, wk, v->w_max);
-                        } else {
-                            orc_alg3_step(&v->T[k], &v->P[k], sd / v->delta, pk, v->q_hat);
-                        }
+                        /* Algorithm 2 keeps its weight sum W in P's place */
+                        double u = pk;
+                        if (v->rule == ORC_RULE_RUNNING)
+                            u = v->w;
+                        else if (v->rule == ORC_RULE_WEIGHTED)
+                            u = v->weight_kind == ORC_WEIGHT_INV_VARIANCE ? 1.0 / pk : v->w;
+                        fuse_measurement(v->rule, &v->T[k], &v->P[k], sd / v->delta, u, v->q_hat, v->w_max);
                         s.updates++;
                     }
         }

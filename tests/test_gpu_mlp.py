@@ -4,7 +4,8 @@ Gates: features (depth and radial exact to float rounding, edge distance
 exact, incidence cosine within 1e-6); network output within 1e-4 relative on
 99.9 % of samples (bfloat16 rounding of a hidden activation can flip where
 the float and double pre-activations straddle a rounding boundary); batch
-gradient within 1e-3 of its largest component; Adam equal to torch.optim.Adam.
+gradient within 1e-3 of its largest component; Adam equal to the oracle's
+float64 update and to torch.optim.Adam.
 """
 
 import math
@@ -110,18 +111,29 @@ def test_batch_visiting_order(mlp):
     assert np.abs(grad.cpu().numpy() - og).max() <= 1e-3 * np.abs(og).max()
 
 
-def test_adam_matches_torch(mlp):
+def test_adam_matches_oracle_and_torch(mlp):
+    """Five GPU Adam steps against the float64 oracle update (and against
+    torch.optim.Adam); the bf16 parameters are the rounding of the masters."""
+    from oracle.adam import adam_step
+
     p0 = trained_like_params(mlp, 6)
     tr = mlp.NoiseTrainer(p0, lr=1e-3)
     w = torch.nn.Parameter(torch.tensor(p0, dtype=torch.float32))
     opt = torch.optim.Adam([w], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    ow = np.asarray(p0, np.float32).astype(np.float64)
+    om, ov = np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
     rng = np.random.default_rng(7)
-    for _ in range(5):
+    for step in range(1, 6):
         g = rng.normal(0, 1e-2, mlp.N_PARAMS).astype(np.float32)
         tr.step(torch.tensor(g, device="cuda"))
         w.grad = torch.tensor(g)
         opt.step()
+        ow, om, ov = adam_step(ow, om, ov, g.astype(np.float64), step)
     torch.cuda.synchronize()
+    gpu = tr.master.cpu().numpy().astype(np.float64)
+    # float32 state: each weight rounds at 2^-24 relative; 1 - 0.999^t in float
+    # is off by 1.3e-5 relative, i.e. ~6e-9 per step of size ~lr
+    np.testing.assert_allclose(gpu, ow, rtol=1e-6, atol=5e-8)
     np.testing.assert_allclose(tr.master.cpu().numpy(), w.detach().numpy(), rtol=1e-5, atol=1e-7)
     ref_bits = w.detach().to(torch.bfloat16).to(torch.float32).numpy()
     np.testing.assert_array_equal(tr.params[:mlp.N_PARAMS].float().cpu().numpy(), ref_bits)
