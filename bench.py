@@ -39,24 +39,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_spec(name, frames):
+def make_spec(name):
+    """The defined sequence of a workload (c2: 100 frames, c3: 300); a run
+    with --steps N times its first N frames at their defined spacing."""
     from synthetic.configs import config_c1, config_c2, config_c3
 
     if name == "c1":
         return config_c1()
     if name == "c2":
-        return config_c2(n_frames=frames)
+        return config_c2()
     if name == "c3":
-        return config_c3(n_frames=frames)
+        return config_c3()
     raise ValueError(name)
 
 
 def generate(spec, n, device="cuda"):
+    """The first n frames of the sequence (depth maps in HBM, poses)."""
     from synthetic.configs import sequence_frame
 
+    if n > spec.n_frames:
+        raise SystemExit(f"{spec.name} has {spec.n_frames} frames; {n} requested")
     depths, poses = [], []
     for k in range(n):
-        d, p = sequence_frame(spec, k % spec.n_frames, device=device)
+        d, p = sequence_frame(spec, k, device=device)
         depths.append(d.contiguous())
         poses.append(p)
         if (k + 1) % 50 == 0:
@@ -142,6 +147,17 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
     return res
 
 
+# Tracking gate: over the timed frames of the orbit (7.5 cm and 3.6 degrees
+# between frames), the estimate must stay within these bounds of the truth.
+TRACK_MAX_TRANSLATION_M = 0.02
+TRACK_FINAL_ROTATION_DEG = 1.0
+
+
+def rotation_error_deg(Ra, Rb):
+    R = np.asarray(Ra)[:, :3] @ np.asarray(Rb)[:, :3].T
+    return math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(R) - 1.0) / 2.0))))
+
+
 def run_tracking(spec, frames, seq, iters=10):
     """Fusion driven by its own pose estimates: frame 0 is fused at its true
     pose; every later frame is registered (ICP, `iters` iterations) against
@@ -158,7 +174,7 @@ def run_tracking(spec, frames, seq, iters=10):
     est = np.asarray(poses[0], np.float64).copy()
     vol.integrate(depths[0], K, est)
     torch.cuda.synchronize()
-    errs = []
+    errs, rots = [], []
     t0 = time.perf_counter()
     for k in range(1, frames):
         vol.raycast(K, est, vert, nrm)
@@ -166,14 +182,18 @@ def run_tracking(spec, frames, seq, iters=10):
         est = icp.results[iters - 1, :12].cpu().numpy().reshape(3, 4).copy()   # the one sync per frame
         vol.integrate(depths[k], K, est)
         errs.append(float(np.linalg.norm(est[:, 3] - poses[k][:, 3])))
+        rots.append(rotation_error_deg(est, poses[k]))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / (frames - 1)
-    R_err = est[:, :3] @ np.asarray(poses[frames - 1])[:, :3].T
-    ang = math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(R_err) - 1.0) / 2.0))))
+    spacing = float(np.linalg.norm(np.asarray(poses[1])[:, 3] - np.asarray(poses[0])[:, 3]))
+    ok = max(errs) <= TRACK_MAX_TRANSLATION_M and rots[-1] <= TRACK_FINAL_ROTATION_DEG
     return {"workload": spec.name, "stage": "tracking", "frames": frames, "icp_iterations_per_frame": iters,
-            "ms_per_frame": round(ms, 3), "fps": round(1e3 / ms, 1),
+            "frame_spacing_m": round(spacing, 5), "ms_per_frame": round(ms, 3), "fps": round(1e3 / ms, 1),
             "final_translation_error_m": round(errs[-1], 5), "max_translation_error_m": round(max(errs), 5),
-            "final_rotation_error_deg": round(ang, 4)}
+            "final_rotation_error_deg": round(rots[-1], 4), "max_rotation_error_deg": round(max(rots), 4),
+            "tracking_ok": bool(ok),
+            "tracking_bound": f"max translation error <= {TRACK_MAX_TRANSLATION_M} m and final rotation "
+                              f"error <= {TRACK_FINAL_ROTATION_DEG} deg"}
 
 
 def run_evict(res):
@@ -415,34 +435,53 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     return res
 
 
-def cpu_baseline(spec, frames=2, ray_pixels=2000):
-    """The oracle (as it stands) on the host: `frames` frames of integration
-    and a seeded sample of raycast pixels of the last frame."""
+def cpu_baseline(spec, frames, max_frames=40, budget_s=12.0, ray_pixels=2000):
+    """The oracle (as it stands) on this host, on the timed frames: the first
+    frames of the sequence in order, integrated single-threaded (until
+    `max_frames` frames or `budget_s` seconds) and then the same frames on all
+    the threads OpenMP may use; then a seeded sample of raycast pixels of the
+    last of them, on one thread and on all."""
     import oracle
-    from synthetic.configs import sequence_frame
 
     oracle.build(force=False)
-    ov = oracle.OracleVolume.from_grid(spec.grid, q_hat=1e-4)
+    depths, poses = frames
     K = spec.K
-    upd = 0
-    t_int = 0.0
-    pose = None
-    for k in range(frames):
-        d, pose = sequence_frame(spec, k)
+    Kv = (K.fx, K.fy, K.cx, K.cy)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = int(omp) if omp and omp.isdigit() and int(omp) > 0 else (os.cpu_count() or 1)
+    host = np.stack([d.cpu().numpy() for d in depths[:max_frames]])
+    out = {}
+    n_used = None
+    for th in (1, threads):
+        ov = oracle.OracleVolume.from_grid(spec.grid, q_hat=1e-4)
+        ov.set_threads(th)
+        upd, t_int, n = 0, 0.0, 0
+        for k in range(len(host) if n_used is None else n_used):
+            t0 = time.perf_counter()
+            upd += ov.integrate(host[k], Kv, poses[k])["updates"]
+            t_int += time.perf_counter() - t0
+            n += 1
+            if n_used is None and t_int >= budget_s:
+                break
+        n_used = n
+        rng = np.random.default_rng(7)
+        m = ray_pixels * (1 if th == 1 else 4)
+        pix = np.stack([rng.integers(0, K.width, m), rng.integers(0, K.height, m)], 1)
         t0 = time.perf_counter()
-        st = ov.integrate(d.numpy(), (K.fx, K.fy, K.cx, K.cy), pose)
-        t_int += time.perf_counter() - t0
-        upd += st["updates"]
-    rng = np.random.default_rng(7)
-    pix = np.stack([rng.integers(0, K.width, ray_pixels), rng.integers(0, K.height, ray_pixels)], 1)
-    t0 = time.perf_counter()
-    ov.raycast((K.fx, K.fy, K.cx, K.cy), pose, K.width, K.height, pixels=pix, n_threads=1)
-    t_ray = time.perf_counter() - t0
-    return dict(value=upd / t_int, unit="voxel-updates/s", cores=1, kind="oracle",
-                raycast_mpix_s=ray_pixels / t_ray / 1e6,
-                sample=f"{spec.name}: integration of frames 0-{frames - 1} ({upd} updates, {t_int:.1f} s) and "
-                       f"raycast of {ray_pixels} seeded pixels of frame {frames - 1} ({t_ray:.1f} s), "
-                       f"single thread, host cpu_count={os.cpu_count()}")
+        ov.raycast(Kv, poses[n - 1], K.width, K.height, pixels=pix, n_threads=th)
+        t_ray = time.perf_counter() - t0
+        out[th] = dict(value=upd / t_int, updates=upd, seconds=round(t_int, 2),
+                       raycast_mpix_s=m / t_ray / 1e6, ray_pixels=m)
+        del ov
+    single, multi = out[1], out[threads]
+    return dict(value=multi["value"], unit="voxel-updates/s", cores=threads, kind="oracle",
+                raycast_mpix_s=multi["raycast_mpix_s"],
+                single_thread={"value": single["value"], "raycast_mpix_s": single["raycast_mpix_s"], "cores": 1},
+                host_cpu_count=os.cpu_count(), omp_num_threads=omp,
+                sample=f"{spec.name}: integration of frames 0-{n_used - 1} in order ({multi['updates']} updates; "
+                       f"{single['seconds']} s on 1 thread, {multi['seconds']} s on {threads}) and raycast of "
+                       f"{single['ray_pixels']} / {multi['ray_pixels']} seeded pixels of frame {n_used - 1}; "
+                       f"host cpu_count={os.cpu_count()}, OMP_NUM_THREADS={omp}")
 
 
 def compare_storage(a, b):
@@ -466,22 +505,31 @@ def compare_storage(a, b):
     return out
 
 
+def variant_line(r, **extra):
+    d = {"workload": r["workload"], "storage": r["storage"], "frames": r["frames"],
+         "voxel_updates_per_s": round(r["voxel_updates_per_s"], 1), "raycast_mpix_s": round(r["raycast_mpix_s"], 2),
+         "stage_us_per_frame": {"prep": round(r["prep_avg_us"], 2), "fuse": round(r["fuse_avg_us"], 2),
+                                "range": round(r["range_avg_us"], 2), "raycast": round(r["raycast_avg_us"], 2)},
+         "updates_per_frame": r["updates"] // r["frames"]}
+    d.update(extra)
+    return d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20, help="frames timed: the first N of the sequence")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"],
+                    help="c3: 1280x960 hand, 4096^3 grid (the headline); c2: 640x480 orbit, 2048^3")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16"])
-    ap.add_argument("--variants", type=int, default=1, help="also run the 4096^3 hand sequence in FP32 and FP16")
-    ap.add_argument("--variant-steps", type=int, default=300)
+    ap.add_argument("--variants", type=int, default=1,
+                    help="also FP16 storage and the learned variance on the same frames")
+    ap.add_argument("--orbit", type=int, default=1,
+                    help="also the 640x480 orbit (its first --steps frames): FP32, Algorithms 1 and 2, "
+                         "ICP, tracking and eviction")
     ap.add_argument("--batch", type=int, default=1, help="also run the 16-scene batched workload")
     ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
-    ap.add_argument("--icp", type=int, default=1, help="also time point-to-plane ICP on the fused volume")
-    ap.add_argument("--rules", type=int, default=1, help="also run the orbit with Algorithms 1 and 2")
-    ap.add_argument("--evict", type=int, default=1, help="also time block eviction on the fused volume")
-    ap.add_argument("--tracking", type=int, default=1,
-                    help="also run the sequence on its own ICP pose estimates (fuse, raycast, register)")
     ap.add_argument("--icp-iters", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -506,8 +554,9 @@ def main():
         log(f"reference copy: {n} bytes read, {n} bytes written")
         del src, dst
     storage = 1 if args.storage == "f16" else 0
-    spec = make_spec(args.config, args.steps)
-    res = run_sequence(spec, storage, args.steps, args.warmup)
+    spec = make_spec(args.config)
+    frames = generate(spec, max(args.steps, args.warmup))
+    res = run_sequence(spec, storage, args.steps, args.warmup, frames=frames)
     raycast_footprint(res, spec, storage, args.steps)
     log(json.dumps({k: v for k, v in res.items() if not k.startswith("_")}))
     out = {
@@ -521,10 +570,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": res["workload"], "frames": args.steps, "grid": res["grid"],
-                   "voxel_mm": res["voxel_mm"], "frame": f"{res['width']}x{res['height']}",
+        "config": {"workload": res["workload"], "frames": args.steps, "sequence_frames": spec.n_frames,
+                   "grid": res["grid"], "voxel_mm": res["voxel_mm"], "frame": f"{res['width']}x{res['height']}",
                    "storage": res["storage"], "parallelism": "single-gpu"},
         "raycast_mpix_s": round(res["raycast_mpix_s"], 2),
         "stage_us_per_frame": {"prep": round(res["prep_avg_us"], 2), "fuse": round(res["fuse_avg_us"], 2),
@@ -534,58 +583,56 @@ def main():
         "roofline": roofline_of(res),
     }
     variants = []
+    tracking_ok = True
     if args.variants:
+        if storage == 0:
+            # FP16 storage on the same frames, against this FP32 run
+            r16 = run_sequence(spec, 1, args.steps, args.warmup, frames=frames)
+            raycast_footprint(r16, spec, 1, args.steps)
+            variants.append(variant_line(r16, roofline=roofline_of(r16), vs_f32=compare_storage(r16["_vol"],
+                                                                                                 res["_vol"])))
+            log(json.dumps({k: v for k, v in r16.items() if not k.startswith("_")}))
+            del r16
         # learned variance on the same frames (network cost does not depend on the weights)
         import paper_1311_7194_amd.mlp as M
 
         params = M.params_from_values(M.init_params(0))
-        rl = run_sequence(spec, storage, args.steps, args.warmup, noise=params, frames=res["_frames"])
-        variants.append({"workload": rl["workload"], "noise": "learned-mlp", "storage": rl["storage"],
-                         "frames": rl["frames"], "voxel_updates_per_s": round(rl["voxel_updates_per_s"], 1),
-                         "prep_us_per_frame": round(rl["prep_avg_us"], 2),
-                         "vs_plain_prep_us_per_frame": round(res["prep_avg_us"], 2),
-                         "updates_per_frame": rl["updates"] // rl["frames"]})
+        rl = run_sequence(spec, storage, args.steps, args.warmup, noise=params, frames=frames)
+        variants.append(variant_line(rl, noise="learned-mlp", vs_plain_prep_us_per_frame=round(res["prep_avg_us"], 2)))
         log(json.dumps({k: v for k, v in rl.items() if not k.startswith("_")}))
         del rl
-    if args.rules:
+    if args.orbit:
+        if args.config == "c2":
+            spec2, r2, frames2 = spec, res, frames
+        else:
+            spec2 = make_spec("c2")
+            n2 = min(max(args.steps, args.warmup), spec2.n_frames)
+            frames2 = generate(spec2, n2)
+            r2 = run_sequence(spec2, 0, min(args.steps, n2), args.warmup, frames=frames2)
+            raycast_footprint(r2, spec2, 0, r2["frames"])
+            variants.append(variant_line(r2, roofline=roofline_of(r2)))
+            log(json.dumps({k: v for k, v in r2.items() if not k.startswith("_")}))
         # Algorithms 1 and 2 on the same frames (the same candidates and decisions, another update)
         for name, rule in (("alg1-running w=0.1", (1, 0, 0.1, math.inf)),
                            ("alg2-weighted w=1 cap 64", (2, 0, 1.0, 64.0))):
-            rr = run_sequence(spec, storage, args.steps, args.warmup, frames=res["_frames"], rule=rule)
+            rr = run_sequence(spec2, 0, r2["frames"], args.warmup, frames=frames2, rule=rule)
             variants.append({"workload": rr["workload"], "update_rule": name, "storage": rr["storage"],
                              "frames": rr["frames"], "voxel_updates_per_s": round(rr["voxel_updates_per_s"], 1),
                              "fuse_us_per_frame": round(rr["fuse_avg_us"], 2),
                              "updates_per_frame": rr["updates"] // rr["frames"]})
             log(json.dumps({k: v for k, v in rr.items() if not k.startswith("_")}))
             del rr
-    if args.icp:
-        ri = run_icp(res, spec, iters=args.icp_iters)
+        ri = run_icp(r2, spec2, iters=args.icp_iters)
         log(json.dumps(ri))
         variants.append(ri)
-    if args.tracking:
-        rt = run_tracking(spec, args.steps, res["_frames"])
+        rt = run_tracking(spec2, r2["frames"], frames2, iters=args.icp_iters)
         log(json.dumps(rt))
         variants.append(rt)
-    if args.evict:
-        re_ = run_evict(res)
+        tracking_ok = rt["tracking_ok"]
+        re_ = run_evict(r2)
         log(json.dumps(re_))
         variants.append(re_)
-    if args.variants and args.config != "c3":
-        spec3 = make_spec("c3", args.variant_steps)
-        r32 = run_sequence(spec3, 0, args.variant_steps, 3)
-        raycast_footprint(r32, spec3, 0, args.variant_steps)
-        r16 = run_sequence(spec3, 1, args.variant_steps, 3)
-        raycast_footprint(r16, spec3, 1, args.variant_steps)
-        cmp = compare_storage(r16["_vol"], r32["_vol"])
-        for r in (r32, r16):
-            variants.append({"workload": r["workload"], "storage": r["storage"], "frames": r["frames"],
-                             "voxel_updates_per_s": round(r["voxel_updates_per_s"], 1),
-                             "raycast_mpix_s": round(r["raycast_mpix_s"], 2),
-                             "updates_per_frame": r["updates"] // r["frames"],
-                             "roofline": roofline_of(r)})
-            log(json.dumps({k: v for k, v in r.items() if not k.startswith("_")}))
-        variants[-1]["vs_f32"] = cmp
-        del r32, r16
+        del r2
     if args.batch:
         rb = run_batch_c5(args.batch_steps or None)
         log(json.dumps(rb))
@@ -594,8 +641,11 @@ def main():
         out["variants"] = variants
     if args.cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(make_spec(args.config, 2))
+        out["cpu_baseline"] = cpu_baseline(spec, (frames[0][:args.steps], frames[1][:args.steps]))
     print(json.dumps(out), flush=True)
+    if not tracking_ok:
+        log("tracking left its bound (see the tracking entry): failing the run")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

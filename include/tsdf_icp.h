@@ -105,8 +105,8 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
  * their eigen-decomposition from the previous iteration's eigenvectors (kept
  * in the workspace), which the nearly unchanged system needs only a sweep or
  * two to finish; the result is the same decomposition to rounding.  Same
- * errors as tsdf_icp_step, and TSDF_EINVAL for a non-finite initial pose or
- * iters out of range. */
+ * errors as tsdf_icp_step, and TSDF_EINVAL for an initial pose that is not a
+ * finite rotation (as the model pose) or iters out of range. */
 tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
                          const float *model_normal_dev, const double model_pose_c2w[12],
                          const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,

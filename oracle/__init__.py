@@ -78,6 +78,8 @@ def lib():
             getattr(L, name).argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.orc_alg2_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_set_rule.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        L.orc_set_threads.argtypes = [P, ctypes.c_int32]
+        L.orc_set_threads.restype = ctypes.c_int
         L.orc_evict.argtypes = [P, P, P, P, P, P, ctypes.c_int64]
         L.orc_evict.restype = ctypes.c_int64
         L.orc_set_rule.restype = ctypes.c_int
@@ -138,6 +140,11 @@ class OracleVolume:
         rc = lib().orc_set_rule(self.h, int(rule), int(weight_kind), float(w), float(w_max))
         if rc != 0:
             raise ValueError(f"oracle set_rule failed with status {rc}")
+
+    def set_threads(self, n_threads: int):
+        """Threads of later integrations (1: the serial loop over pixels)."""
+        if lib().orc_set_threads(self.h, int(n_threads)) != 0:
+            raise ValueError("oracle set_threads: n_threads must be >= 1")
 
     def integrate(self, depth, K, pose, noise_kind: int = NOISE_QUADRATIC, coeff: float = 0.0015,
                   phat: Optional[np.ndarray] = None) -> dict:

@@ -32,6 +32,7 @@ struct orc_volume {
     int32_t rule;        /* ORC_RULE_*: which update algorithm fuses measurements */
     int32_t weight_kind; /* ORC_WEIGHT_*: w_k of Algorithms 1 and 2 */
     double w, w_max;     /* constant weight; cap of the weight sum (Algorithm 2) */
+    int32_t threads;     /* integration threads (1: the plain serial loop) */
     int32_t *offset;     /* N0*N1*N2 entries: block index or -1 */
     int32_t *keys;       /* cap*3 block coordinates, allocation order */
     double *T, *P;       /* cap*512 each */
@@ -81,6 +82,7 @@ orc_volume *orc_create(const int32_t dims[3], double voxel_size, const double or
     v->weight_kind = ORC_WEIGHT_CONSTANT;
     v->w = 1.0;
     v->w_max = INFINITY;
+    v->threads = 1;
     v->cap = capacity_blocks;
     v->offset = (int32_t *)malloc(sizeof(int32_t) * nb);
     for (int64_t b = 0; b < nb; ++b) v->offset[b] = -1;
@@ -113,22 +115,35 @@ static int64_t table_index(const orc_volume *v, int bx, int by, int bz)
 
 /* Offset-table lookup, then allocation from the store when absent (the
  * paper's free list reduces to "next unused block" here). Returns -1 when the
- * store is full. */
+ * store is full.  With several integration threads (orc_set_threads) the
+ * lookup reads the table entry atomically and an absent block is allocated
+ * inside a critical section, which initialises it before publishing its
+ * offset. */
 static int64_t block_of(orc_volume *v, int bx, int by, int bz, int allocate, int64_t *new_blocks)
 {
     int64_t ti = table_index(v, bx, by, bz);
-    if (v->offset[ti] >= 0 || !allocate) return v->offset[ti];
-    if (v->n_blocks >= v->cap) return -1;
-    int64_t b = v->n_blocks++;
-    v->offset[ti] = (int32_t)b;
-    v->keys[3 * b + 0] = bx;
-    v->keys[3 * b + 1] = by;
-    v->keys[3 * b + 2] = bz;
-    for (int k = 0; k < BVOX; ++k) {
-        v->T[b * BVOX + k] = CHI;
-        v->P[b * BVOX + k] = 0.0;
+    int32_t off;
+#pragma omp atomic read seq_cst
+    off = v->offset[ti];
+    if (off >= 0 || !allocate) return off;
+    int64_t b = -1;
+#pragma omp critical(orc_allocate)
+    {
+        b = v->offset[ti];
+        if (b < 0 && v->n_blocks < v->cap) {
+            b = v->n_blocks++;
+            v->keys[3 * b + 0] = bx;
+            v->keys[3 * b + 1] = by;
+            v->keys[3 * b + 2] = bz;
+            for (int k = 0; k < BVOX; ++k) {
+                v->T[b * BVOX + k] = CHI;
+                v->P[b * BVOX + k] = 0.0;
+            }
+#pragma omp atomic write seq_cst
+            v->offset[ti] = (int32_t)b;
+            if (new_blocks) ++*new_blocks;
+        }
     }
-    if (new_blocks) ++*new_blocks;
     return b;
 }
 
@@ -296,6 +311,65 @@ static void cell_box(const camera *c, int i, int j, double z0, double z1, double
     }
 }
 
+/*
+ * The measurements of pixel (i, j): every voxel whose measurement is not chi
+ * projects to exactly one pixel and lies in that pixel's frustum cell over
+ * [D - delta, D + delta]; scanning the cell and keeping only the voxels that
+ * project back to (i, j) visits each such voxel exactly once over the frame.
+ * Returns ORC_EFULL when the block store runs out.
+ */
+static int integrate_pixel(orc_volume *v, const camera *c, const float *depth, int i, int j, int32_t noise_kind,
+                           double coeff, const double *phat_px, orc_stats *s)
+{
+    const int32_t W = c->W;
+    const double pad = 1e-3 * v->vs;
+    float D = depth[(int64_t)j * W + i];
+    if (!(D > 0.0f) || !isfinite(D)) return ORC_OK;
+    double z0 = fmax((double)D - v->delta, 0.0), z1 = (double)D + v->delta;
+    double lo[3], hi[3];
+    int g0[3], g1[3];
+    cell_box(c, i, j, z0, z1, lo, hi);
+    for (int a = 0; a < 3; ++a) {
+        double a0 = ceil((lo[a] - pad - v->origin[a]) / v->vs - 0.5);
+        double a1 = floor((hi[a] + pad - v->origin[a]) / v->vs - 0.5);
+        if (a0 < 0) a0 = 0;
+        if (a1 > v->G[a] - 1) a1 = v->G[a] - 1;
+        if (a0 > a1) return ORC_OK;
+        g0[a] = (int)a0;
+        g1[a] = (int)a1;
+    }
+    double pk = measurement_variance(v, noise_kind, coeff, phat_px, (int64_t)j * W + i, (double)D);
+    /* Algorithm 2 keeps its weight sum W in P's place */
+    double u = pk;
+    if (v->rule == ORC_RULE_RUNNING)
+        u = v->w;
+    else if (v->rule == ORC_RULE_WEIGHTED)
+        u = v->weight_kind == ORC_WEIGHT_INV_VARIANCE ? 1.0 / pk : v->w;
+    for (int gz = g0[2]; gz <= g1[2]; ++gz)
+        for (int gy = g0[1]; gy <= g1[1]; ++gy)
+            for (int gx = g0[0]; gx <= g1[0]; ++gx) {
+                int pi, pj, tie = 0;
+                double sd;
+                s->visited++;
+                if (!measure(v, c, depth, gx, gy, gz, &pi, &pj, &sd, &tie)) continue;
+                if (pi != i || pj != j) continue;
+                if (tie) s->ties++;
+                int64_t b = block_of(v, gx / BLOCK, gy / BLOCK, gz / BLOCK, 1, &s->new_blocks);
+                if (b < 0) return ORC_EFULL;
+                int64_t k = b * BVOX + (gx % BLOCK) + BLOCK * (gy % BLOCK) + BLOCK * BLOCK * (gz % BLOCK);
+                fuse_measurement(v->rule, &v->T[k], &v->P[k], sd / v->delta, u, v->q_hat, v->w_max);
+                s->updates++;
+            }
+    return ORC_OK;
+}
+
+int orc_set_threads(orc_volume *v, int32_t n_threads)
+{
+    if (!v || n_threads < 1) return ORC_EINVAL;
+    v->threads = n_threads;
+    return ORC_OK;
+}
+
 int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const double K[4],
                   const double pose[12], int32_t noise_kind, double coeff, const double *phat_px,
                   orc_stats *st)
@@ -305,57 +379,36 @@ int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const
     camera c;
     load_camera(&c, K, pose, W, H);
     orc_stats s = {0, 0, 0, 0};
-    const double pad = 1e-3 * v->vs;
     int status = ORC_OK;
-    /* Every voxel whose measurement is not chi projects to exactly one
-     * pixel and lies in that pixel's frustum cell over [D - delta, D + delta];
-     * scanning each pixel's cell and keeping only the voxels that project
-     * back to that pixel visits each such voxel exactly once. */
-    for (int j = 0; j < H && status == ORC_OK; ++j) {
-        for (int i = 0; i < W && status == ORC_OK; ++i) {
-            float D = depth[(int64_t)j * W + i];
-            if (!(D > 0.0f) || !isfinite(D)) continue;
-            double z0 = fmax((double)D - v->delta, 0.0), z1 = (double)D + v->delta;
-            double lo[3], hi[3];
-            int g0[3], g1[3];
-            cell_box(&c, i, j, z0, z1, lo, hi);
-            int empty = 0;
-            for (int a = 0; a < 3; ++a) {
-                double a0 = ceil((lo[a] - pad - v->origin[a]) / v->vs - 0.5);
-                double a1 = floor((hi[a] + pad - v->origin[a]) / v->vs - 0.5);
-                if (a0 < 0) a0 = 0;
-                if (a1 > v->G[a] - 1) a1 = v->G[a] - 1;
-                if (a0 > a1) empty = 1;
-                g0[a] = (int)a0;
-                g1[a] = (int)a1;
-            }
-            if (empty) continue;
-            double pk = measurement_variance(v, noise_kind, coeff, phat_px, (int64_t)j * W + i, (double)D);
-            for (int gz = g0[2]; gz <= g1[2] && status == ORC_OK; ++gz)
-                for (int gy = g0[1]; gy <= g1[1] && status == ORC_OK; ++gy)
-                    for (int gx = g0[0]; gx <= g1[0]; ++gx) {
-                        int pi, pj, tie = 0;
-                        double sd;
-                        s.visited++;
-                        if (!measure(v, &c, depth, gx, gy, gz, &pi, &pj, &sd, &tie)) continue;
-                        if (pi != i || pj != j) continue;
-                        if (tie) s.ties++;
-                        int64_t b = block_of(v, gx / BLOCK, gy / BLOCK, gz / BLOCK, 1, &s.new_blocks);
-                        if (b < 0) {
-                            status = ORC_EFULL;
-                            break;
-                        }
-                        int64_t k = b * BVOX + (gx % BLOCK) + BLOCK * (gy % BLOCK) + BLOCK * BLOCK * (gz % BLOCK);
-                        /* Algorithm 2 keeps its weight sum W in P's place */
-                        double u = pk;
-                        if (v->rule == ORC_RULE_RUNNING)
-                            u = v->w;
-                        else if (v->rule == ORC_RULE_WEIGHTED)
-                            u = v->weight_kind == ORC_WEIGHT_INV_VARIANCE ? 1.0 / pk : v->w;
-                        fuse_measurement(v->rule, &v->T[k], &v->P[k], sd / v->delta, u, v->q_hat, v->w_max);
-                        s.updates++;
-                    }
+    if (v->threads <= 1) {
+        for (int j = 0; j < H && status == ORC_OK; ++j)
+            for (int i = 0; i < W && status == ORC_OK; ++i)
+                status = integrate_pixel(v, &c, depth, i, j, noise_kind, coeff, phat_px, &s);
+    } else {
+        /* each voxel belongs to one pixel, so rows of pixels update disjoint
+         * voxels; only the block store is shared */
+        int64_t upd = 0, nb = 0, ties = 0, vis = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(v->threads) reduction(+ : upd, nb, ties, vis)
+        for (int j = 0; j < H; ++j) {
+            orc_stats r = {0, 0, 0, 0};
+            int full;
+#pragma omp atomic read
+            full = status;
+            for (int i = 0; i < W && full == ORC_OK; ++i)
+                if (integrate_pixel(v, &c, depth, i, j, noise_kind, coeff, phat_px, &r) != ORC_OK) {
+                    full = ORC_EFULL;
+#pragma omp atomic write
+                    status = ORC_EFULL;
+                }
+            upd += r.updates;
+            nb += r.new_blocks;
+            ties += r.ties;
+            vis += r.visited;
         }
+        s.updates = upd;
+        s.new_blocks = nb;
+        s.ties = ties;
+        s.visited = vis;
     }
     if (st) *st = s;
     return status;

@@ -48,6 +48,10 @@ int64_t orc_block_count(const orc_volume *v);
  *   CONSTANT : p_hat = coeff (already in delta^2 units)
  *   PER_PIXEL: p_hat = phat_px[j*W+i] (delta^2 units)
  * Returns ORC_EFULL (and stops) when the block store is exhausted. */
+/* Threads of later integrations (default 1, the serial loop over pixels).
+ * More threads split the rows of pixels; the results are the same, only
+ * the allocation order of new blocks may differ. */
+int orc_set_threads(orc_volume *v, int32_t n_threads);
 int orc_integrate(orc_volume *v, const float *depth, int32_t W, int32_t H, const double K[4],
                   const double pose[12], int32_t noise_kind, double coeff, const double *phat_px,
                   orc_stats *st);

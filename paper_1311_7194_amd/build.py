@@ -24,16 +24,34 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-                             "-o", tmp] + sources()
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
+    return res.returncode
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles each source to an object in parallel, then links libtsdf.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    cmds = [[HIPCC] + compile_flags + inc + ["-c", s, "-o", o] for s, o in zip(srcs, objs)]
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 16)
+    with ThreadPoolExecutor(jobs) as ex:
+        rcs = list(ex.map(lambda c: _run(c, verbose), cmds))
+    if any(rcs):
         raise RuntimeError("hipcc failed building libtsdf.so")
+    tmp = LIB + ".tmp"
+    if _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs, verbose):
+        raise RuntimeError("hipcc failed linking libtsdf.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -188,8 +188,14 @@ tsdf_status tsdf_evict_blocks(tsdf_volume *vol, const int32_t lo[3], const int32
     hipError_t e = hipMemcpyAsync(&ds, v.state, sizeof(ds), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return TSDF_EHIP;
-    const uint32_t n = ds.pool_count < v.capacity ? ds.pool_count : v.capacity;
     *n_out = 0;
+    if (ds.status != 0) {
+        // a pool, hash or candidate overflow left the volume incomplete (and
+        // possibly a reserved slot without a block): refuse, as later calls do
+        volume_note_flags(vol, ds.status);
+        return TSDF_EFULL;
+    }
+    const uint32_t n = ds.pool_count < v.capacity ? ds.pool_count : v.capacity;
     if (n == 0) return TSDF_OK;
     // count, and stop before any change if the evicted blocks do not fit
     hipLaunchKernelGGL(evict_fill_kernel, dim3(1), dim3(256), 0, stream, (uint32_t *)c, (uint64_t)64, 0u);

@@ -622,9 +622,7 @@ tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const
                          hipStream_t stream)
 {
     IcpArgs a;
-    if (!pose_init_c2w || iters < 1 || iters > 1024) return TSDF_EINVAL;
-    for (int q = 0; q < 12; ++q)
-        if (!isfinite(pose_init_c2w[q])) return TSDF_EINVAL;
+    if (!pose_init_c2w || iters < 1 || iters > 1024 || !icp_pose_ok(pose_init_c2w)) return TSDF_EINVAL;
     const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
                                     workspace_dev, workspace_bytes, results_dev, a);
     if (st != TSDF_OK) return st;

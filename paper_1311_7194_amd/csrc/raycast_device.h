@@ -96,9 +96,10 @@ __device__ __forceinline__ void range_block(const VolumeView &v, const Camera &c
     // in its block's box of non-chi voxels: q in [8B + lo, 8B + hi + 1] with
     // x = origin + (q + 1/2) voxel; a block without such voxels adds nothing
     const uint32_t box = v.block_box[slot];
-    if (!(box & kBoxValid)) return;
+    const uint32_t key = v.pool_keys[slot];
+    if (!(box & kBoxValid) || key == kEmptyKey) return;   // no voxels, or a slot whose insertion failed
     int bx, by, bz;
-    unpack_key(v.pool_keys[slot], bx, by, bz);
+    unpack_key(key, bx, by, bz);
     const float bwx = (float)((box_hi(box, 0) - box_lo(box, 0) + 1) * v.vs);
     const float bwy = (float)((box_hi(box, 1) - box_lo(box, 1) + 1) * v.vs);
     const float bwz = (float)((box_hi(box, 2) - box_lo(box, 2) + 1) * v.vs);

@@ -148,6 +148,8 @@ __device__ inline int32_t hash_insert_unique(const VolumeView &v, uint32_t key)
         if ((uint32_t)(prev & 0xffffffffu) == key) return (int32_t)(prev >> 32);
         h = (h + 1) & v.hash_mask;
     }
+    // the slot stays reserved but holds no block: passes over the pool skip it
+    v.pool_keys[slot] = kEmptyKey;
     atomicOr(&v.state->status, (uint32_t)TSDF_FLAG_HASH_FULL);
     return -1;
 }
@@ -257,5 +259,7 @@ hipError_t launch_import(const VolumeView &v, const int32_t *keys, const void *T
 // TSDF_EFULL once a sticky device flag has been seen.
 VolumeView volume_view(const tsdf_volume *vol);
 tsdf_status volume_enqueue(tsdf_volume *vol, hipStream_t s, uint32_t *stamp);
+// Records sticky device flags the caller has read back (later calls return TSDF_EFULL).
+void volume_note_flags(tsdf_volume *vol, uint32_t flags);
 
 }  // namespace tsdf

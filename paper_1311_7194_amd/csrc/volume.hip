@@ -235,6 +235,8 @@ tsdf_status volume_enqueue(tsdf_volume *vol, hipStream_t s, uint32_t *stamp)
     return TSDF_OK;
 }
 
+void volume_note_flags(tsdf_volume *vol, uint32_t flags) { vol->host_flags |= flags; }
+
 }  // namespace tsdf
 
 static hipEvent_t take_event(tsdf_volume *v)

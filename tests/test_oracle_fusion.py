@@ -326,13 +326,37 @@ def test_sparse_equals_dense_orbit_sequence(oracle_lib):
     compare_sparse_dense(vol, dense)
 
 
+def test_threaded_integration_equals_serial(oracle_lib):
+    """Rows of pixels on several threads give the same blocks, values and
+    counts as the serial loop (only the allocation order may differ)."""
+    spec = small_orbit(width=64, height=48, n_frames=3, G=96, vs=0.02)
+    vols = []
+    stats = []
+    for threads in (1, 4):
+        vol = oracle.OracleVolume.from_grid(spec.grid, q_hat=1e-4)
+        vol.set_threads(threads)
+        st = []
+        for k in range(spec.n_frames):
+            d, p = sequence_frame(spec, k)
+            st.append(vol.integrate(d.numpy(), Kvec(spec.K), p))
+        vols.append(oracle.sorted_blocks(*vol.export()))
+        stats.append(st)
+    assert stats[0] == stats[1]
+    for a, b in zip(*vols):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        oracle.OracleVolume.from_grid(spec.grid).set_threads(0)
+
+
 def test_capacity_exhaustion_reports_full(oracle_lib):
     spec = config_c1()
     depth, pose = sequence_frame(spec, 0)
-    vol = oracle.OracleVolume.from_grid(spec.grid, capacity_blocks=10)
-    with pytest.raises(RuntimeError):
-        vol.integrate(depth.numpy(), Kvec(spec.K), pose)
-    assert vol.n_blocks == 10
+    for threads in (1, 4):
+        vol = oracle.OracleVolume.from_grid(spec.grid, capacity_blocks=10)
+        vol.set_threads(threads)
+        with pytest.raises(RuntimeError):
+            vol.integrate(depth.numpy(), Kvec(spec.K), pose)
+        assert vol.n_blocks == 10
 
 
 def test_memory_formula(oracle_lib):
