@@ -21,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c")]
+_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c"), os.path.join(_HERE, "mc.c")]
 
 HIT, AMBIGUOUS, BISECT_INVALID, MARGINAL = 1, 2, 4, 8
 NOISE_QUADRATIC, NOISE_CONSTANT, NOISE_PER_PIXEL = 0, 1, 2
@@ -91,6 +91,10 @@ def lib():
         L.orc_mlp_loss_grad.restype = ctypes.c_double
         L.orc_mlp_loss_grad.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int32]
         L.orc_alg3_step.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_mc_case.restype = ctypes.c_int
+        L.orc_mc_case.argtypes = [ctypes.c_int32, P]
+        L.orc_marching_cubes.restype = ctypes.c_int64
+        L.orc_marching_cubes.argtypes = [P, P, P, P, ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -205,6 +209,17 @@ class OracleVolume:
             raise RuntimeError("oracle evict failed")
         return keys[:n], T[:n], P[:n]
 
+    def marching_cubes(self):
+        """Triangles of the zero level set (mc.c): vertex ids [n,3] int64,
+        edge parameters t [n,3] and world positions [n,3,3], float64."""
+        n = int(lib().orc_marching_cubes(self.h, None, None, None, 0))
+        vid = np.zeros((n, 3), np.int64)
+        t = np.zeros((n, 3))
+        pos = np.zeros((n, 3, 3))
+        m = lib().orc_marching_cubes(self.h, _ptr(vid), _ptr(t), _ptr(pos), n)
+        assert m == n
+        return vid, t, pos
+
     def set_block(self, key, T, P=None):
         k = np.ascontiguousarray(np.asarray(key, np.int32))
         t = _f64(T).reshape(512)
@@ -282,6 +297,18 @@ def mlp_variance(depth, K, params, delta: float, coeff: float = 0.0015) -> np.nd
     pq = (coeff * D * D / delta) ** 2
     pl = np.exp(s) / (delta * delta)
     return np.where(valid & (D > 0), np.clip(pl, pq * math.exp(-4.0), pq * math.exp(4.0)), pq)
+
+
+MC_MAX_TRIS = 8
+
+
+def mc_case(c: int) -> np.ndarray:
+    """Triangles of marching-cubes case c as cube-edge numbers [n,3] (mc.c)."""
+    e = np.zeros(3 * MC_MAX_TRIS, np.int32)
+    n = lib().orc_mc_case(int(c), _ptr(e))
+    if n < 0:
+        raise ValueError("case index")
+    return e[:3 * n].reshape(n, 3)
 
 
 def sorted_blocks(keys: np.ndarray, *arrays):

@@ -632,3 +632,30 @@ int orc_set_block(orc_volume *v, const int32_t key[3], const double *T, const do
     }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------- accessors */
+
+void orc_geometry(const orc_volume *v, int32_t dims[3], double *voxel_size, double origin[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        dims[a] = v->G[a];
+        origin[a] = v->origin[a];
+    }
+    *voxel_size = v->vs;
+}
+
+int orc_block_key(const orc_volume *v, int64_t b, int32_t key[3])
+{
+    if (b < 0 || b >= v->n_blocks) return ORC_EINVAL;
+    for (int a = 0; a < 3; ++a) key[a] = v->keys[3 * b + a];
+    return ORC_OK;
+}
+
+int orc_voxel(const orc_volume *v, int32_t gx, int32_t gy, int32_t gz, double *T)
+{
+    if (gx < 0 || gy < 0 || gz < 0 || gx >= v->G[0] || gy >= v->G[1] || gz >= v->G[2]) return 0;
+    int32_t b = v->offset[table_index(v, gx / BLOCK, gy / BLOCK, gz / BLOCK)];
+    if (b < 0) return 0;
+    *T = v->T[(int64_t)b * BVOX + (gx % BLOCK) + BLOCK * (gy % BLOCK) + BLOCK * BLOCK * (gz % BLOCK)];
+    return 1;
+}

@@ -101,6 +101,30 @@ void orc_alg1_step(double *T, double Tk, double w);
 void orc_alg2_step(double *T, double *Wsum, double Tk, double w, double w_max);
 void orc_alg3_step(double *T, double *P, double Tk, double pk, double q);
 
+/* Grid of the volume: voxels per axis, voxel edge (m), min corner (m). */
+void orc_geometry(const orc_volume *v, int32_t dims[3], double *voxel_size, double origin[3]);
+/* Coordinates of the b-th block in allocation order. */
+int orc_block_key(const orc_volume *v, int64_t b, int32_t key[3]);
+/* Stored T_hat of voxel g: returns 1 when its block is allocated, else 0. */
+int orc_voxel(const orc_volume *v, int32_t gx, int32_t gy, int32_t gz, double *T);
+
+/* Marching cubes over the allocated blocks (mc.c).  The case table: for
+ * cube index c (bit k set when corner k is inside, F < 0; corner k at offset
+ * (k & 1, k >> 1 & 1, k >> 2 & 1)), up to ORC_MC_MAX_TRIS triangles given by
+ * cube-edge numbers, -1 terminated; edge 4a + m runs along axis a from the
+ * corner whose other two coordinates are (m & 1, m >> 1) in increasing axis
+ * order.  Returns the number of triangles of case c. */
+#define ORC_MC_MAX_TRIS 8
+int orc_mc_case(int32_t c, int32_t edges[3 * ORC_MC_MAX_TRIS]);
+/* Triangles of every cell of the grid whose eight corners are valid (block
+ * allocated, |T_hat| <= 1).  Cells are visited block by block in allocation
+ * order, cells of a block in order x + 8y + 64z (cell g spans voxel centres
+ * g .. g + 1).  Per triangle: vid[3] vertex ids 3 * (gx + G0 (gy + G1 gz)) + a
+ * of the crossed edge (from voxel g along axis a), t[3] the edge parameter
+ * F(g) / (F(g) - F(g + e_a)), pos[9] world positions.  Writes min(n, cap)
+ * triangles (any output may be NULL) and returns n. */
+int64_t orc_marching_cubes(const orc_volume *v, int64_t *vid, double *t, double *pos, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif
