@@ -35,6 +35,7 @@ EXPORTED = [
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
     "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step", "tsdf_icp_run",
     "tsdf_set_update_rule", "tsdf_evict_workspace_bytes", "tsdf_evict_blocks",
+    "tsdf_mesh_case", "tsdf_mesh_workspace_bytes", "tsdf_extract_mesh",
 ]
 
 
@@ -131,9 +132,13 @@ def lib():
         L.tsdf_icp_workspace_bytes.restype = ctypes.c_uint64
         L.tsdf_icp_step.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_uint64, P, P]
         L.tsdf_icp_run.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint64, P, P]
+        L.tsdf_mesh_case.argtypes = [ctypes.c_int32, P]
+        L.tsdf_mesh_workspace_bytes.argtypes = [P]
+        L.tsdf_mesh_workspace_bytes.restype = ctypes.c_uint64
+        L.tsdf_extract_mesh.argtypes = [P, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P, P]
         for name in EXPORTED:
             if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy",
-                            "tsdf_icp_workspace_bytes", "tsdf_evict_workspace_bytes"):
+                            "tsdf_icp_workspace_bytes", "tsdf_evict_workspace_bytes", "tsdf_mesh_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -162,8 +167,8 @@ def _pose_array(pose) -> np.ndarray:
     return p
 
 
-def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
-    return ctypes.c_void_p(t.data_ptr())
+def _ptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
 class Volume:
@@ -331,6 +336,36 @@ class Volume:
                                        stream_handle(stream)), "tsdf_evict_blocks")
         m = int(n.value)
         return keys[:m], T[:m], P[:m]
+
+    def mesh_workspace(self) -> torch.Tensor:
+        """A device workspace for extract_mesh (reusable across calls)."""
+        return torch.empty(int(lib().tsdf_mesh_workspace_bytes(self.handle)), dtype=torch.uint8,
+                           device=self.buffer.device)
+
+    def extract_mesh_into(self, vid: Optional[torch.Tensor], t: Optional[torch.Tensor], xyz: Optional[torch.Tensor],
+                          count: torch.Tensor, work: torch.Tensor, stream=None):
+        """tsdf_extract_mesh into caller tensors (no synchronisation): vid
+        int64 [cap,3], t float32 [cap,3], xyz float32 [cap,3,3] or None,
+        count a one-element int64 device tensor."""
+        cap = 0 if vid is None else int(vid.shape[0])
+        _check(lib().tsdf_extract_mesh(self.handle, _ptr(vid), _ptr(t), _ptr(xyz), ctypes.c_uint64(cap),
+                                       _ptr(work), ctypes.c_uint64(work.numel()), _ptr(count),
+                                       stream_handle(stream)), "tsdf_extract_mesh")
+
+    def extract_mesh(self, with_xyz: bool = True, stream=None):
+        """Marching cubes over the allocated blocks (tsdf_mesh.h): returns
+        (vertex ids [n,3] int64, t [n,3] float32, world positions [n,3,3]
+        float32 or None) as device tensors.  Counts first, then extracts."""
+        dev = self.buffer.device
+        work = self.mesh_workspace()
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.extract_mesh_into(None, None, None, count, work, stream)
+        n = int(count.item())
+        vid = torch.empty((max(n, 1), 3), dtype=torch.int64, device=dev)
+        t = torch.empty((max(n, 1), 3), dtype=torch.float32, device=dev)
+        xyz = torch.empty((max(n, 1), 3, 3), dtype=torch.float32, device=dev) if with_xyz else None
+        self.extract_mesh_into(vid, t, xyz, count, work, stream)
+        return vid[:n], t[:n], (xyz[:n] if with_xyz else None)
 
     def import_blocks(self, keys: torch.Tensor, T: torch.Tensor, P: torch.Tensor, stream=None):
         keys = keys.to(device=self.buffer.device, dtype=torch.int32).contiguous()

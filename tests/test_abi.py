@@ -170,3 +170,27 @@ def test_evict_host_validation_without_volume(lib):
     work = ctypes.c_void_p(1 << 20)                     # never dereferenced: the call returns first
     assert lib.tsdf_evict_blocks(None, lo, lo, None, None, None, 0, work, 1 << 20, ctypes.byref(n), None) == T.EINVAL
     assert n.value == 7
+
+
+def test_mesh_case_table_equals_the_oracle_table(lib):
+    # the library derives its marching-cubes table at compile time, the
+    # oracle at run time, each from the rule stated in tsdf_mesh.h; the two
+    # derivations are separate code and must agree on every case
+    import oracle
+
+    oracle.build(force=False)
+    edges = (ctypes.c_int32 * 15)()
+    for c in range(256):
+        n = lib.tsdf_mesh_case(c, edges)
+        ref = oracle.mc_case(c)
+        assert n == len(ref), c
+        assert list(edges)[:3 * n] == ref.ravel().tolist(), c
+        assert all(e == -1 for e in list(edges)[3 * n:]), c
+    assert lib.tsdf_mesh_case(256, edges) == -1 and lib.tsdf_mesh_case(-1, edges) == -1
+    assert lib.tsdf_mesh_case(0, None) == -1
+
+
+def test_mesh_host_validation_without_volume(lib):
+    assert lib.tsdf_mesh_workspace_bytes(None) == 0
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: the call returns first
+    assert lib.tsdf_extract_mesh(None, fake, fake, None, 1, fake, 1 << 20, fake, None) == T.EINVAL
