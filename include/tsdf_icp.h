@@ -113,6 +113,23 @@ tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const
                          void *workspace_dev, uint64_t workspace_bytes, tsdf_icp_result *results_dev,
                          hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * allocation-free serving loops): tsdf_icp_run without a workspace argument.
+ * Its partial sums and warm-start eigenvectors live in a static array of the
+ * library, 164,128 bytes per device (the partials of at most 512 workgroups,
+ * enough for every frame size tsdf_icp_workspace_bytes accepts), reserved on
+ * each device the library runs on until the process ends.  The call
+ * allocates nothing.  Results are bitwise those of tsdf_icp_run with a
+ * workspace.  All calls on one device share that array, so calls whose work
+ * may overlap on one device (several streams, or several host threads) race
+ * and must be serialised by the caller.  Same arguments and errors as
+ * tsdf_icp_run; TSDF_EINVAL also for a frame size outside 1..16384 per axis,
+ * TSDF_EHIP when the array's device address cannot be obtained. */
+tsdf_status tsdf_icp_run_noalloc(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                                 const float *model_normal_dev, const double model_pose_c2w[12],
+                                 const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,
+                                 tsdf_icp_result *results_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

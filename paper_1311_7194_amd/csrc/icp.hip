@@ -16,6 +16,8 @@
 // expressions decide them.
 #include <math.h>
 
+#include <mutex>
+
 #include <hip/hip_runtime.h>
 
 #include "tsdf_icp.h"
@@ -533,6 +535,38 @@ bool icp_pose_ok(const double *p)
 }
 
 }  // namespace
+
+// Scratch memory of tsdf_icp_run_noalloc: the per-workgroup partial sums of
+// at most kIcpMaxGroups workgroups (the cap of icp_groups, whatever the frame
+// size) followed by the 36 warm-start eigenvector entries, the layout the
+// caller's workspace has in tsdf_icp_run.  Each device holds its own copy
+// from the first call on it until the process ends.
+constexpr int kScratchDoubles = kIcpMaxGroups * kPartial + 36;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's `scratch` (in host code the name
+// stands for a host-side shadow, never for device memory); looked up once
+// per device with that device current.  nullptr on failure.
+double *scratch_address()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 }  // namespace tsdf
 
 using namespace tsdf;
@@ -550,18 +584,17 @@ uint64_t tsdf_icp_workspace_bytes(int32_t width, int32_t height)
 
 namespace {
 
-// Validates the arguments shared by tsdf_icp_step and tsdf_icp_run and fills the kernel arguments.
+// Validates the arguments shared by the ICP entry points (all but the
+// workspace) and fills the kernel arguments.
 tsdf_status icp_args(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
                      const float *model_normal_dev, const double *model_pose_c2w, const tsdf_icp_params *params,
-                     void *workspace_dev, uint64_t workspace_bytes, const void *result_dev, IcpArgs &a)
+                     const void *result_dev, IcpArgs &a)
 {
-    if (!depth_dev || !K || !model_vertex_dev || !model_normal_dev || !model_pose_c2w || !params ||
-        !workspace_dev || !result_dev)
+    if (!depth_dev || !K || !model_vertex_dev || !model_normal_dev || !model_pose_c2w || !params || !result_dev)
         return TSDF_EINVAL;
     if (!(isfinite(K->fx) && isfinite(K->fy) && isfinite(K->cx) && isfinite(K->cy) && K->fx > 0 && K->fy > 0))
         return TSDF_EINVAL;
-    const uint64_t need = tsdf_icp_workspace_bytes(K->width, K->height);
-    if (need == 0 || workspace_bytes < need) return TSDF_EINVAL;
+    if (tsdf_icp_workspace_bytes(K->width, K->height) == 0) return TSDF_EINVAL;
     if (!icp_pose_ok(model_pose_c2w)) return TSDF_EINVAL;
     if (!(isfinite(params->dist_max) && params->dist_max > 0) ||
         !(isfinite(params->cos_min) && params->cos_min >= -1.0 && params->cos_min <= 1.0) ||
@@ -609,11 +642,42 @@ tsdf_status tsdf_icp_step(const float *depth_dev, const tsdf_intrinsics *K, cons
     IcpArgs a;
     if (!pose_dev) return TSDF_EINVAL;
     const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
-                                    workspace_dev, workspace_bytes, result_dev, a);
+                                    result_dev, a);
     if (st != TSDF_OK) return st;
+    if (!workspace_dev || workspace_bytes < tsdf_icp_workspace_bytes(K->width, K->height)) return TSDF_EINVAL;
     icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, pose_dev, a, workspace_dev, result_dev, 0, stream);
     return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Validates the arguments of a chain of iterations (all but the workspace).
+tsdf_status icp_run_args(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                         const float *model_normal_dev, const double *model_pose_c2w, const double *pose_init_c2w,
+                         const tsdf_icp_params *params, int32_t iters, const void *results_dev, IcpArgs &a)
+{
+    if (!pose_init_c2w || iters < 1 || iters > 1024 || !icp_pose_ok(pose_init_c2w)) return TSDF_EINVAL;
+    const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
+                                    results_dev, a);
+    if (st != TSDF_OK) return st;
+    for (int q = 0; q < 12; ++q) a.P0[q] = pose_init_c2w[q];
+    return TSDF_OK;
+}
+
+tsdf_status icp_run_enqueue(const float *depth_dev, const float *mv, const float *mn, const IcpArgs &a, int32_t iters,
+                            void *workspace_dev, tsdf_icp_result *results_dev, hipStream_t stream)
+{
+    for (int k = 0; k < iters; ++k)
+        icp_enqueue(depth_dev, mv, mn, k == 0 ? nullptr : results_dev[k - 1].pose, a, workspace_dev, results_dev + k,
+                    k > 0, stream);
+    return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
 
 tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
                          const float *model_normal_dev, const double model_pose_c2w[12],
@@ -622,15 +686,30 @@ tsdf_status tsdf_icp_run(const float *depth_dev, const tsdf_intrinsics *K, const
                          hipStream_t stream)
 {
     IcpArgs a;
-    if (!pose_init_c2w || iters < 1 || iters > 1024 || !icp_pose_ok(pose_init_c2w)) return TSDF_EINVAL;
-    const tsdf_status st = icp_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w, params,
-                                    workspace_dev, workspace_bytes, results_dev, a);
+    const tsdf_status st = icp_run_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w,
+                                        pose_init_c2w, params, iters, results_dev, a);
     if (st != TSDF_OK) return st;
-    for (int q = 0; q < 12; ++q) a.P0[q] = pose_init_c2w[q];
-    for (int k = 0; k < iters; ++k)
-        icp_enqueue(depth_dev, model_vertex_dev, model_normal_dev, k == 0 ? nullptr : results_dev[k - 1].pose, a,
-                    workspace_dev, results_dev + k, k > 0, stream);
-    return hipGetLastError() == hipSuccess ? TSDF_OK : TSDF_EHIP;
+    if (!workspace_dev || workspace_bytes < tsdf_icp_workspace_bytes(K->width, K->height)) return TSDF_EINVAL;
+    return icp_run_enqueue(depth_dev, model_vertex_dev, model_normal_dev, a, iters, workspace_dev, results_dev,
+                           stream);
+}
+
+tsdf_status tsdf_icp_run_noalloc(const float *depth_dev, const tsdf_intrinsics *K, const float *model_vertex_dev,
+                                 const float *model_normal_dev, const double model_pose_c2w[12],
+                                 const double pose_init_c2w[12], const tsdf_icp_params *params, int32_t iters,
+                                 tsdf_icp_result *results_dev, hipStream_t stream)
+{
+    IcpArgs a;
+    const tsdf_status st = icp_run_args(depth_dev, K, model_vertex_dev, model_normal_dev, model_pose_c2w,
+                                        pose_init_c2w, params, iters, results_dev, a);
+    if (st != TSDF_OK) return st;
+    // the frame-size check above bounds the workgroups at kIcpMaxGroups, so
+    // the partials always fit; checked again against the array itself
+    if (tsdf_icp_workspace_bytes(K->width, K->height) > sizeof(double) * (uint64_t)kScratchDoubles)
+        return TSDF_EINVAL;
+    double *ws = scratch_address();
+    if (!ws) return TSDF_EHIP;
+    return icp_run_enqueue(depth_dev, model_vertex_dev, model_normal_dev, a, iters, ws, results_dev, stream);
 }
 
 }  // extern "C"

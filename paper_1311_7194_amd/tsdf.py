@@ -34,7 +34,7 @@ EXPORTED = [
     "tsdf_batch_bytes", "tsdf_batch_create", "tsdf_batch_destroy", "tsdf_batch_set_graph",
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
     "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step", "tsdf_icp_run",
-    "tsdf_set_update_rule", "tsdf_evict_workspace_bytes", "tsdf_evict_blocks",
+    "tsdf_set_update_rule", "tsdf_evict_workspace_bytes", "tsdf_evict_blocks", "tsdf_icp_run_noalloc",
     "tsdf_mesh_case", "tsdf_mesh_workspace_bytes", "tsdf_extract_mesh",
 ]
 
@@ -132,6 +132,7 @@ def lib():
         L.tsdf_icp_workspace_bytes.restype = ctypes.c_uint64
         L.tsdf_icp_step.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_uint64, P, P]
         L.tsdf_icp_run.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_uint64, P, P]
+        L.tsdf_icp_run_noalloc.argtypes = [P, P, P, P, P, P, P, ctypes.c_int32, P, P]
         L.tsdf_mesh_case.argtypes = [ctypes.c_int32, P]
         L.tsdf_mesh_workspace_bytes.argtypes = [P]
         L.tsdf_mesh_workspace_bytes.restype = ctypes.c_uint64
@@ -521,6 +522,19 @@ class Icp:
                                   ctypes.byref(self.params), int(iters), _ptr(self.workspace),
                                   ctypes.c_uint64(self.workspace.numel()), _ptr(self.results),
                                   stream_handle(stream)), "tsdf_icp_run")
+        return self.results[iters - 1, :12]
+
+    def run_noalloc(self, depth: torch.Tensor, model_vertex: torch.Tensor, model_normal: torch.Tensor, model_pose,
+                    pose, iters: int, stream=None) -> torch.Tensor:
+        """`run` through tsdf_icp_run_noalloc: the library's static scratch
+        array instead of this object's workspace."""
+        if not 1 <= iters <= self.results.shape[0]:
+            raise ValueError("iters")
+        mp, p0 = _pose_array(model_pose), _pose_array(pose)
+        _check(lib().tsdf_icp_run_noalloc(_ptr(depth), ctypes.byref(self.K), _ptr(model_vertex), _ptr(model_normal),
+                                          mp.ctypes.data_as(ctypes.c_void_p), p0.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(self.params), int(iters), _ptr(self.results),
+                                          stream_handle(stream)), "tsdf_icp_run_noalloc")
         return self.results[iters - 1, :12]
 
     def result(self, k: int = 0) -> dict:

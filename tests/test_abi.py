@@ -172,6 +172,27 @@ def test_evict_host_validation_without_volume(lib):
     assert n.value == 7
 
 
+def test_icp_run_noalloc_host_validation(lib):
+    # every argument error is reported before the call looks up its device array
+    K = T.Intrinsics(525.0, 525.0, 319.5, 239.5, 640, 480)
+    eye = (ctypes.c_double * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    prm = T.IcpParams(0.02, 0.9, 0.005, 1, 0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+
+    def run(K=K, pose=eye, iters=1, null=None):
+        args = [fake, ctypes.byref(K), fake, fake, eye, pose, ctypes.byref(prm), iters, fake, None]
+        if null is not None:
+            args[null] = None
+        return lib.tsdf_icp_run_noalloc(*args)
+
+    for k in (0, 1, 2, 3, 4, 5, 6, 8):
+        assert run(null=k) == T.EINVAL, k
+    assert run(iters=0) == T.EINVAL and run(iters=1025) == T.EINVAL
+    assert run(K=T.Intrinsics(525.0, 525.0, 319.5, 239.5, 16385, 480)) == T.EINVAL
+    assert run(K=T.Intrinsics(525.0, 525.0, 319.5, 239.5, 640, 0)) == T.EINVAL
+    assert run(pose=(ctypes.c_double * 12)(-1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)) == T.EINVAL
+
+
 def test_mesh_case_table_equals_the_oracle_table(lib):
     # the library derives its marching-cubes table at compile time, the
     # oracle at run time, each from the rule stated in tsdf_mesh.h; the two
