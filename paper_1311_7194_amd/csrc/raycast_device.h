@@ -372,26 +372,35 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
     static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "group size");
     const int lane = threadIdx.x & 63;
     const int j = lane & (G - 1);                       // sample slot inside the ray's group
-    // rays in 8x8-pixel tile order: 64 consecutive rays form one tile
-    const long long ray = gt / G;
-    const long long tile = ray >> 6;
-    const int within = (int)(ray & 63);
-    const int ti = (int)(tile % tiles_x), tj = (int)(tile / tiles_x);
+    // rays in 8x8-pixel tile order: 64 consecutive rays form one tile (the
+    // launch covers fewer than 2^31 rays)
+    const int ray = (int)(gt / G);
+    const int tile = ray >> 6;
+    const int within = ray & 63;
+    const int ti = tile % tiles_x, tj = tile / tiles_x;
     const int i = ti * kRT + (within & 7), jpix = tj * kRT + (within >> 3);
     const bool active = tj < tiles_y && i < cam.width && jpix < cam.height;
     const double h = 0.5 * v.vs;
 
     Ray r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.q0[a] = r.dq[a] = r.inv[a] = r.d[a] = 0.0;
     int n_lo = 1, n_end = 0;   // sample indices (a ray crosses the grid in fewer than 2^31 samples)
+    float zmin_t = 0.0f, zmax_t = -1.0f;
+    bool near = false;
     if (active) {
         const size_t t = (size_t)tj * tiles_x + ti;
         // the pixel's cell span joined with its tile's (blocks with large footprints)
         const int cw = (cam.width + kCell - 1) / kCell, ch = (cam.height + kCell - 1) / kCell;
         const size_t cell = (size_t)(jpix / kCell) * cw + i / kCell;
-        const float zmin_t = __uint_as_float(min(v.tile_range[t], v.pix_range[cell]));
-        const float zmax_t =
+        zmin_t = __uint_as_float(min(v.tile_range[t], v.pix_range[cell]));
+        zmax_t =
             __uint_as_float(max(v.tile_range[(size_t)tiles_x * tiles_y + t], v.pix_range[(size_t)cw * ch + cell]));
-        const bool near = v.state->near_stamp == stamp;
+        near = v.state->near_stamp == stamp;
+    }
+    // a ray with an empty span (and no block at the camera plane) misses
+    // without a sample: the ray itself is only set up for the others
+    if (active && (near || zmin_t <= zmax_t)) {
         const double dc0 = (i - cam.cx) / cam.fx, dc1 = (jpix - cam.cy) / cam.fy;
         const double len = sqrt(dc0 * dc0 + dc1 * dc1 + 1.0);
 #pragma unroll
@@ -403,7 +412,7 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         }
         // valid samples need every stencil voxel in the grid: q in [0, G-1]
         double s_in = 0.0, s_out = 1e300;
-        bool miss = !(near || zmin_t <= zmax_t);
+        bool miss = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double hiq = (double)(v.dims[a] - 1);
