@@ -124,11 +124,12 @@ static_assert(kMcTableHost.ntri[0] == 0 && kMcTableHost.ntri[255] == 0 && kMcTab
 
 __constant__ McTable kMcTable = kMcTableHost;
 
-constexpr int kMcThreads = 512;      // one lane per cell of a block
+constexpr int kMcLanes = 64;         // one wavefront per block: lane (x, y) takes the cells of its z column
 constexpr int kTile = 9;             // corner tile edge
 constexpr int kHalo = 217;           // 3 * 64 + 3 * 8 + 1 neighbour values
-constexpr uint32_t kMcGrid = 4096;   // workgroups striding over the pool
+constexpr uint32_t kMcGrid = 16384;  // single-wavefront workgroups striding over the pool
 constexpr uint32_t kScanTile = 1024; // slots per first-level scan tile
+constexpr int kOwnerChunk = 1024;    // output triangles of a block placed per round
 
 template <typename S>
 __device__ __forceinline__ float mc_load(const S *p);
@@ -137,19 +138,20 @@ __device__ __forceinline__ float mc_load<float>(const float *p) { return *p; }
 template <>
 __device__ __forceinline__ float mc_load<__half>(const __half *p) { return __half2float(*p); }
 
-struct TileLds {
-    float f[kTile * kTile * kTile];
-    int32_t nslot[8];
-    uint32_t wsum[kMcThreads / 64];
+struct McLds {
+    float f[kTile * kTile * kTile];   // corner tile, x fastest
+    int32_t nslot[8];                 // pool slots of the +x/+y/+z neighbours (-1: none)
+    uint8_t cases[kBlockVoxels];      // case of each cell (0 when invalid)
+    uint16_t owner[kOwnerChunk];      // emit: cell | triangle << 9 of each output triangle of a round
 };
 
 __device__ __forceinline__ int tidx(int x, int y, int z) { return x + kTile * y + kTile * kTile * z; }
 
 // Fills L.f with the corner tile of the block in `slot` (key `key`): chi
 // where a neighbour block is unallocated or outside the grid.  Ends with a
-// barrier.
+// barrier (of the one-wavefront workgroup).
 template <typename S>
-__device__ void load_tile(const VolumeView &v, uint32_t slot, uint32_t key, TileLds &L)
+__device__ void load_tile(const VolumeView &v, uint32_t slot, uint32_t key, McLds &L)
 {
     const int t = threadIdx.x;
     int bx, by, bz;
@@ -167,46 +169,67 @@ __device__ void load_tile(const VolumeView &v, uint32_t slot, uint32_t key, Tile
         }
         L.nslot[t] = s;
     }
-    const S *T = (const S *)v.poolT;
-    L.f[tidx(t & 7, (t >> 3) & 7, t >> 6)] = mc_load<S>(T + (size_t)slot * kBlockVoxels + t);
+    const S *T = (const S *)v.poolT + (size_t)slot * kBlockVoxels;
+    float own[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) own[z] = mc_load<S>(T + t + 64 * z);   // 64 consecutive voxels per z
+#pragma unroll
+    for (int z = 0; z < 8; ++z) L.f[tidx(t & 7, t >> 3, z)] = own[z];
     __syncthreads();
-    if (t < kHalo) {
-        int n, lx = 0, ly = 0, lz = 0;   // neighbour (bits x, y, z) and its voxel
-        if (t < 64) {
-            n = 1, ly = t & 7, lz = t >> 3;
-        } else if (t < 128) {
-            n = 2, lx = t & 7, lz = (t >> 3) & 7;
-        } else if (t < 192) {
-            n = 4, lx = t & 7, ly = (t >> 3) & 7;
-        } else if (t < 200) {
-            n = 3, lz = t - 192;
-        } else if (t < 208) {
-            n = 5, ly = t - 200;
-        } else if (t < 216) {
-            n = 6, lx = t - 208;
-        } else {
-            n = 7;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int h = t + 64 * r;
+        if (h < kHalo) {
+            int n, lx = 0, ly = 0, lz = 0;   // neighbour (bits x, y, z) and its voxel
+            if (h < 64) {
+                n = 1, ly = h & 7, lz = h >> 3;
+            } else if (h < 128) {
+                n = 2, lx = h & 7, lz = (h >> 3) & 7;
+            } else if (h < 192) {
+                n = 4, lx = h & 7, ly = (h >> 3) & 7;
+            } else if (h < 200) {
+                n = 3, lz = h - 192;
+            } else if (h < 208) {
+                n = 5, ly = h - 200;
+            } else if (h < 216) {
+                n = 6, lx = h - 208;
+            } else {
+                n = 7;
+            }
+            const int32_t s = L.nslot[n];
+            const float val = s < 0 ? kChi : mc_load<S>((const S *)v.poolT + (size_t)s * kBlockVoxels + lx + 8 * ly + 64 * lz);
+            L.f[tidx((n & 1) ? 8 : lx, (n & 2) ? 8 : ly, (n & 4) ? 8 : lz)] = val;
         }
-        const int32_t s = L.nslot[n];
-        const float val = s < 0 ? kChi : mc_load<S>(T + (size_t)s * kBlockVoxels + lx + 8 * ly + 64 * lz);
-        L.f[tidx((n & 1) ? 8 : lx, (n & 2) ? 8 : ly, (n & 4) ? 8 : lz)] = val;
     }
     __syncthreads();
 }
 
-// Case of this lane's cell (0 when invalid) and its eight corner values.
-__device__ __forceinline__ int cell_case(const TileLds &L, float f[8])
+// Cases of the eight cells of this lane's column (cell x + 8y + 64z, z = 0..7;
+// 0 when a corner is not a distance), walking up the column so that each
+// z-layer of corners is read once.
+__device__ __forceinline__ void column_cases(const McLds &L, int cs[8])
 {
-    const int t = threadIdx.x, x = t & 7, y = (t >> 3) & 7, z = t >> 6;
-    bool ok = true;
-    int c = 0;
+    const int t = threadIdx.x, x = t & 7, y = t >> 3;
+    float lo[4];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        f[k] = L.f[tidx(x + (k & 1), y + ((k >> 1) & 1), z + (k >> 2))];
-        ok = ok && fabsf(f[k]) <= 1.0f;
-        c |= (f[k] < 0.0f ? 1 : 0) << k;
+    for (int k = 0; k < 4; ++k) lo[k] = L.f[tidx(x + (k & 1), y + (k >> 1), 0)];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        float hi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hi[k] = L.f[tidx(x + (k & 1), y + (k >> 1), z + 1)];
+        bool ok = true;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ok = ok && fabsf(lo[k]) <= 1.0f && fabsf(hi[k]) <= 1.0f;
+            c |= (lo[k] < 0.0f ? 1 : 0) << k;
+            c |= (hi[k] < 0.0f ? 1 : 0) << (k + 4);
+        }
+        cs[z] = ok ? c : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lo[k] = hi[k];
     }
-    return ok ? c : 0;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t x)
@@ -228,9 +251,9 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x)
 }
 
 template <typename S>
-__global__ __launch_bounds__(kMcThreads) void mc_count_kernel(VolumeView v, uint32_t *__restrict__ counts)
+__global__ __launch_bounds__(kMcLanes) void mc_count_kernel(VolumeView v, uint32_t *__restrict__ counts)
 {
-    __shared__ TileLds L;
+    __shared__ McLds L;
     const uint32_t n = min(v.state->pool_count, v.capacity);
     for (uint32_t slot = blockIdx.x; slot < n; slot += gridDim.x) {
         const uint32_t key = v.pool_keys[slot];
@@ -239,17 +262,14 @@ __global__ __launch_bounds__(kMcThreads) void mc_count_kernel(VolumeView v, uint
             continue;
         }
         load_tile<S>(v, slot, key, L);
-        float f[8];
-        const uint32_t nt = wave_sum(kMcTable.ntri[cell_case(L, f)]);
-        if (__lane_id() == 0) L.wsum[threadIdx.x >> 6] = nt;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t s = 0;
+        int cs[8];
+        column_cases(L, cs);
+        uint32_t nt = 0;
 #pragma unroll
-            for (int w = 0; w < kMcThreads / 64; ++w) s += L.wsum[w];
-            counts[slot] = s;
-        }
-        __syncthreads();
+        for (int z = 0; z < 8; ++z) nt += kMcTable.ntri[cs[z]];
+        nt = wave_sum(nt);
+        if (threadIdx.x == 0) counts[slot] = nt;
+        __syncthreads();   // the next block's tile overwrites this one
     }
 }
 
@@ -319,42 +339,69 @@ __global__ __launch_bounds__(1024) void mc_scan_top_kernel(const VolumeView v, c
     if (threadIdx.x == 0) *count = carry;
 }
 
+// Emit: the block's triangles are placed in rounds of kOwnerChunk; in each
+// round every cell writes, for each of its triangles in the round, its cell
+// and triangle number into `owner` at the triangle's position, then lane k
+// computes and writes the round's triangles k, k + 64, ... (consecutive
+// lanes write consecutive triangles).
 template <typename S>
-__global__ __launch_bounds__(kMcThreads) void mc_emit_kernel(VolumeView v, const uint32_t *__restrict__ counts,
-                                                             const uint32_t *__restrict__ offsets,
-                                                             const unsigned long long *__restrict__ tile_base,
-                                                             unsigned long long cap, long long *__restrict__ vid,
-                                                             float *__restrict__ tpar, float *__restrict__ xyz)
+__global__ __launch_bounds__(kMcLanes) void mc_emit_kernel(VolumeView v, const uint32_t *__restrict__ counts,
+                                                           const uint32_t *__restrict__ offsets,
+                                                           const unsigned long long *__restrict__ tile_base,
+                                                           unsigned long long cap, long long *__restrict__ vid,
+                                                           float *__restrict__ tpar, float *__restrict__ xyz)
 {
-    __shared__ TileLds L;
+    __shared__ McLds L;
     const uint32_t n = min(v.state->pool_count, v.capacity);
+    const int t = threadIdx.x;
+    const long long G0 = v.dims[0], G1 = v.dims[1];
     for (uint32_t slot = blockIdx.x; slot < n; slot += gridDim.x) {
-        if (counts[slot] == 0) continue;   // uniform: no triangles (or no block) in this slot
+        const uint32_t total = counts[slot];
+        if (total == 0) continue;   // uniform: no triangles (or no block) in this slot
+        const unsigned long long base = tile_base[slot / kScanTile] + offsets[slot];
+        if (base >= cap) continue;
         const uint32_t key = v.pool_keys[slot];
         load_tile<S>(v, slot, key, L);
-        float f[8];
-        const int c = cell_case(L, f);
-        const uint32_t nt = kMcTable.ntri[c];
-        const uint32_t inc = wave_inclusive_scan(nt);
-        const int wave = threadIdx.x >> 6;
-        if (__lane_id() == 63) L.wsum[wave] = inc;
-        __syncthreads();
-        unsigned long long first = tile_base[slot / kScanTile] + offsets[slot] + inc - nt;
-        for (int w = 0; w < wave; ++w) first += L.wsum[w];
-        if (nt) {
-            int bx, by, bz;
-            unpack_key(key, bx, by, bz);
-            const int t = threadIdx.x;
-            const long long gx = 8 * bx + (t & 7), gy = 8 * by + ((t >> 3) & 7), gz = 8 * bz + (t >> 6);
-            const long long G0 = v.dims[0], G1 = v.dims[1];
-            for (uint32_t i = 0; i < nt; ++i) {
-                const unsigned long long o = first + i;
+        int cs[8];
+        column_cases(L, cs);
+        // exclusive prefix of the triangle counts in cell order (x + 8y + 64z)
+        uint32_t pre[8], run = 0;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            L.cases[t + 64 * z] = (uint8_t)cs[z];
+            const uint32_t nt = kMcTable.ntri[cs[z]];
+            const uint32_t inc = wave_inclusive_scan(nt);
+            pre[z] = run + inc - nt;
+            run += (uint32_t)__shfl((int)inc, 63);
+        }
+        int bx, by, bz;
+        unpack_key(key, bx, by, bz);
+        for (uint32_t r0 = 0; r0 < total; r0 += kOwnerChunk) {
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                const uint32_t nt = kMcTable.ntri[cs[z]];
+                for (uint32_t i = 0; i < nt; ++i) {
+                    const uint32_t k = pre[z] + i;
+                    if (k >= r0 && k < r0 + kOwnerChunk) L.owner[k - r0] = (uint16_t)((t + 64 * z) | (i << 9));
+                }
+            }
+            __syncthreads();
+            const uint32_t r1 = min(total, r0 + (uint32_t)kOwnerChunk);
+            for (uint32_t k = r0 + t; k < r1; k += kMcLanes) {
+                const unsigned long long o = base + k;
                 if (o >= cap) break;
+                const uint32_t e = L.owner[k - r0];
+                const int cell = (int)(e & 511u), i = (int)(e >> 9);
+                const int c = L.cases[cell];
+                const int cx = cell & 7, cy = (cell >> 3) & 7, cz = cell >> 6;
+                const long long gx = 8 * bx + cx, gy = 8 * by + cy, gz = 8 * bz + cz;
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const int e = kMcTable.edge[c][3 * i + j];
-                    const int a = e >> 2, lo = mc_edge_lo(e), hi = lo | (1 << a);
-                    const float te = f[lo] / (f[lo] - f[hi]);
+                    const int ed = kMcTable.edge[c][3 * i + j];
+                    const int a = ed >> 2, lo = mc_edge_lo(ed), hi = lo | (1 << a);
+                    const float flo = L.f[tidx(cx + (lo & 1), cy + ((lo >> 1) & 1), cz + (lo >> 2))];
+                    const float fhi = L.f[tidx(cx + (hi & 1), cy + ((hi >> 1) & 1), cz + (hi >> 2))];
+                    const float te = flo / (flo - fhi);
                     const long long px = gx + (lo & 1), py = gy + ((lo >> 1) & 1), pz = gz + (lo >> 2);
                     vid[3 * o + j] = 3 * (px + G0 * (py + G1 * pz)) + a;
                     tpar[3 * o + j] = te;
@@ -363,12 +410,12 @@ __global__ __launch_bounds__(kMcThreads) void mc_emit_kernel(VolumeView v, const
                                              (double)py + 0.5 + (a == 1 ? (double)te : 0.0),
                                              (double)pz + 0.5 + (a == 2 ? (double)te : 0.0)};
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) xyz[9 * o + 3 * j + k] = (float)(v.origin[k] + p[k] * v.vs);
+                        for (int q = 0; q < 3; ++q) xyz[9 * o + 3 * j + q] = (float)(v.origin[q] + p[q] * v.vs);
                     }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -430,19 +477,19 @@ tsdf_status tsdf_extract_mesh(tsdf_volume *vol, int64_t *vertex_id_dev, float *t
     const uint32_t tiles = (v.capacity + kScanTile - 1) / kScanTile;
     const bool f16 = v.storage == TSDF_F16;
     if (f16)
-        hipLaunchKernelGGL(mc_count_kernel<__half>, dim3(kMcGrid), dim3(kMcThreads), 0, stream, v, w.counts);
+        hipLaunchKernelGGL(mc_count_kernel<__half>, dim3(kMcGrid), dim3(kMcLanes), 0, stream, v, w.counts);
     else
-        hipLaunchKernelGGL(mc_count_kernel<float>, dim3(kMcGrid), dim3(kMcThreads), 0, stream, v, w.counts);
+        hipLaunchKernelGGL(mc_count_kernel<float>, dim3(kMcGrid), dim3(kMcLanes), 0, stream, v, w.counts);
     hipLaunchKernelGGL(mc_scan_tiles_kernel, dim3(tiles), dim3(256), 0, stream, v, w.counts, w.offsets, w.tile_sum);
     hipLaunchKernelGGL(mc_scan_top_kernel, dim3(1), dim3(1024), 0, stream, v, w.tile_sum, w.tile_base,
                        (unsigned long long *)count_dev);
     if (cap > 0) {
         if (f16)
-            hipLaunchKernelGGL(mc_emit_kernel<__half>, dim3(kMcGrid), dim3(kMcThreads), 0, stream, v, w.counts,
+            hipLaunchKernelGGL(mc_emit_kernel<__half>, dim3(kMcGrid), dim3(kMcLanes), 0, stream, v, w.counts,
                                w.offsets, w.tile_base, (unsigned long long)cap, (long long *)vertex_id_dev, t_dev,
                                xyz_dev);
         else
-            hipLaunchKernelGGL(mc_emit_kernel<float>, dim3(kMcGrid), dim3(kMcThreads), 0, stream, v, w.counts,
+            hipLaunchKernelGGL(mc_emit_kernel<float>, dim3(kMcGrid), dim3(kMcLanes), 0, stream, v, w.counts,
                                w.offsets, w.tile_base, (unsigned long long)cap, (long long *)vertex_id_dev, t_dev,
                                xyz_dev);
     }
