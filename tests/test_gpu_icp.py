@@ -211,3 +211,21 @@ def test_step_chain_equals_run_chain(tsdf):
         assert ra["N"] == rb["N"] and ra["kept"] == rb["kept"], k
         assert np.abs(ra["pose"] - rb["pose"]).max() < 1e-10, k
         assert np.abs(ra["lam"] - rb["lam"]).max() <= 1e-9 * np.abs(rb["lam"]).max(), k
+
+
+def test_tracking_at_the_benchmark_frame_spacing(tsdf):
+    # the benchmark's tracking leg on the first 20 frames of the 100-frame
+    # orbit (7.5 cm and 3.6 degrees between frames): the estimate must stay
+    # within the benchmark's drift bound on every frame
+    import bench
+
+    spec = config_c2()
+    frames = [], []
+    for k in range(20):
+        d, p = sequence_frame(spec, k)
+        frames[0].append(d.cuda())
+        frames[1].append(p)
+    rt = bench.run_tracking(spec, 20, frames, iters=10)
+    print(f"[icp] tracking at the benchmark spacing: {rt}", flush=True)
+    assert rt["frame_spacing_m"] > 0.07
+    assert rt["tracking_ok"], rt
