@@ -378,7 +378,10 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
     const int tile = ray >> 6;
     const int within = ray & 63;
     const int ti = tile % tiles_x, tj = tile / tiles_x;
-    const int i = ti * kRT + (within & 7), jpix = tj * kRT + (within >> 3);
+    // 16 consecutive rays cover one 4x4-pixel cell of the tile: they share
+    // the cell's depth span and mostly the same blocks
+    const int cq = within >> 4, k16 = within & 15;
+    const int i = ti * kRT + (cq & 1) * 4 + (k16 & 3), jpix = tj * kRT + (cq >> 1) * 4 + (k16 >> 2);
     const bool active = tj < tiles_y && i < cam.width && jpix < cam.height;
     const double h = 0.5 * v.vs;
 
