@@ -64,7 +64,7 @@ struct PrepMlpLds {
     union {
         PrepCandLds cand;
         FeatLds feat;
-        MlpWaveLds wave[4];
+        MlpInferLds wave[4];
     } u;
     MlpParamsLds P;
 };
@@ -94,8 +94,7 @@ __device__ __forceinline__ void prep_body(const VolumeView &v, const float *__re
         const bool fok = tile_features(L.u.feat, depth, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
                                        tx * kTile, ty * kTile, tid, f);
         __syncthreads();
-        const float s = mlp_forward_wave(L.P, (const uint16_t *)noise.mlp + MLP_W2, L.u.wave[tid >> 6], f, tid & 63,
-                                         nullptr);
+        const float s = mlp_infer_wave(L.P, (const uint16_t *)noise.mlp, L.u.wave[tid >> 6], f, tid & 63);
         if (valid && fok) {
             const float pl = __expf(s) * inv_delta_f * inv_delta_f;
             ph = fminf(fmaxf(pl, ph * 0.018315639f), ph * 54.59815f);   // [p_q e^-4, p_q e^4]

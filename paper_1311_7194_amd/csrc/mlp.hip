@@ -36,13 +36,14 @@ __global__ __launch_bounds__(256) void forward_kernel(const uint16_t *__restrict
                                                       const float4 *__restrict__ x, int64_t n, float *__restrict__ s)
 {
     __shared__ MlpParamsLds P;
-    __shared__ MlpWaveLds Wl[4];
+    __shared__ MlpInferLds Wl[4];
     mlp_stage_params(P, params, threadIdx.x, 256);
     __syncthreads();
     const int64_t k = blockIdx.x * 256ll + threadIdx.x;
     float4 xv = k < n ? x[k] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
-    const float out = mlp_forward_wave(P, params + MLP_W2, Wl[threadIdx.x >> 6], xa, threadIdx.x & 63, nullptr);
+    // the same forward pass as the integration path
+    const float out = mlp_infer_wave(P, params, Wl[threadIdx.x >> 6], xa, threadIdx.x & 63);
     if (k < n) s[k] = out;
 }
 

@@ -35,10 +35,13 @@ __device__ __forceinline__ uint16_t bf16_bits(float f)
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float((uint32_t)bf16_bits(f) << 16); }
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float silu(float a) { return a / (1.0f + __expf(-a)); }
+// SiLU with the hardware reciprocal (one rounding more than a division; the
+// result is rounded to bfloat16 next).  exp(-a) = inf for very negative a
+// gives rcp(inf) = 0, the limit.
+__device__ __forceinline__ float silu(float a) { return a * __builtin_amdgcn_rcpf(1.0f + __expf(-a)); }
 __device__ __forceinline__ float silu_grad(float a)
 {
-    const float sg = 1.0f / (1.0f + __expf(-a));
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-a));
     return sg * (1.0f + a * (1.0f - sg));
 }
 
@@ -123,6 +126,77 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpParamsLds &P, const u
 #pragma unroll
     for (int o = 0; o < kMlpHidden; ++o) s += w.t3[lane][o];
     return s;
+}
+
+// Inference-only forward pass with a small LDS footprint (the integration
+// path runs it in every preparation workgroup, where LDS bounds occupancy):
+// one bf16 activation tile per wavefront holds h1 for layer 2, then h2 for
+// the output layer, which also runs on the matrix cores (W3 as the only
+// non-zero column of B).  Same rounding points as mlp_forward_wave; only the
+// order of the output layer's FP32 sum differs.
+struct MlpInferLds {
+    uint16_t h[64][kMlpHidden + 4];   // bf16 activations, one sample per row
+    float out[64];
+};
+
+__device__ __forceinline__ float mlp_infer_wave(const MlpParamsLds &P, const uint16_t *__restrict__ params,
+                                                MlpInferLds &w, const float x[4], int lane)
+{
+    const float x0[4] = {bf16_round(x[0]), bf16_round(x[1]), bf16_round(x[2]), bf16_round(x[3])};
+#pragma unroll
+    for (int o = 0; o < kMlpHidden; ++o) {
+        float a = P.p[MLP_B1 + o];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) a += P.p[MLP_W1 + o * kMlpIn + i] * x0[i];
+        w.h[lane][o] = bf16_bits(silu(a));
+    }
+    __syncthreads();
+    const int col = lane & 31, kh = 4 * (lane >> 5);
+    f32x16_t acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < kMlpHidden / 8; ++kk) {
+            bf16x4_t a, b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a[e] = (short)w.h[32 * t + col][8 * kk + kh + e];
+                b[e] = (short)params[MLP_W2 + col * kMlpHidden + 8 * kk + kh + e];
+            }
+            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+        }
+        acc[t] = c;
+    }
+    __syncthreads();   // h1 has been read: the tile now takes h2
+    const float b2 = P.p[MLP_B2 + col];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            w.h[32 * t + 8 * (r >> 2) + kh + (r & 3)][col] = bf16_bits(silu(acc[t][r] + b2));
+    __syncthreads();
+    // s[m] = b3 + sum_o h2[m][o] W3[o]: M = samples, N = 1 (column 0 of B), K = o
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < kMlpHidden / 8; ++kk) {
+            bf16x4_t a, b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a[e] = (short)w.h[32 * t + col][8 * kk + kh + e];
+                b[e] = col == 0 ? (short)params[MLP_W3 + 8 * kk + kh + e] : (short)0;
+            }
+            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+        }
+        if (col == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) w.out[32 * t + 8 * (r >> 2) + kh + (r & 3)] = c[r] + P.p[MLP_B3];
+        }
+    }
+    __syncthreads();
+    return w.out[lane];
 }
 
 }  // namespace tsdf

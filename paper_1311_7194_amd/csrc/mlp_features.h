@@ -10,7 +10,7 @@
 //        a discontinuity is a valid pixel with an in-image 4-neighbour that is
 //        invalid or differs by more than 5 % of its depth.  Exact separable
 //        transform inside the 33x33 window: min over dy of dy^2 + g(dy)^2,
-//        g = nearest discontinuity along the row
+//        g = nearest discontinuity along the row (from the row's bit mask)
 //   f3 = radial pixel distance to the principal point / fx
 #pragma once
 
@@ -26,7 +26,7 @@ constexpr int kFeatDepth = kFeatRegion + 2;              // 50 (depth incl. the 
 
 struct FeatLds {
     float dep[kFeatDepth][kFeatDepth + 1];   // NaN = outside the image, 0 = no measurement
-    uint8_t disc[kFeatRegion][kFeatRegion];
+    unsigned long long disc[kFeatRegion];    // discontinuities of each region row, bit c = column c
     uint8_t g[kFeatRegion][kFeatTile];       // row distance to the nearest discontinuity (17 = none)
 };
 
@@ -47,27 +47,36 @@ __device__ inline bool tile_features(FeatLds &L, const float *__restrict__ depth
         L.dep[r][c] = d;
     }
     __syncthreads();
-    for (int k = tid; k < kFeatRegion * kFeatRegion; k += 256) {
-        const int r = k / kFeatRegion, c = k % kFeatRegion;
-        const float D = L.dep[r + 1][c + 1];
-        uint8_t dsc = 0;
-        if (D > 0.0f) {   // false for NaN and 0
-            const float nb[4] = {L.dep[r + 1][c + 2], L.dep[r + 1][c], L.dep[r + 2][c + 1], L.dep[r][c + 1]};
+    // discontinuity bits: wavefront w takes rows w, w + 4, ..., lane c < 48 one
+    // column, and the row's ballot is its bit mask
+    const int lane = tid & 63;
+    for (int r = tid >> 6; r < kFeatRegion; r += 4) {
+        bool dsc = false;
+        if (lane < kFeatRegion) {
+            const int c = lane;
+            const float D = L.dep[r + 1][c + 1];
+            if (D > 0.0f) {   // false for NaN and 0
+                const float nb[4] = {L.dep[r + 1][c + 2], L.dep[r + 1][c], L.dep[r + 2][c + 1], L.dep[r][c + 1]};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (isnan(nb[q])) continue;   // outside the image: does not count
-                if (!(nb[q] > 0.0f) || fabs((double)nb[q] - (double)D) > 0.05 * (double)D) dsc = 1;
+                for (int q = 0; q < 4; ++q) {
+                    if (isnan(nb[q])) continue;   // outside the image: does not count
+                    if (!(nb[q] > 0.0f) || fabs((double)nb[q] - (double)D) > 0.05 * (double)D) dsc = true;
+                }
             }
         }
-        L.disc[r][c] = dsc;
+        const unsigned long long m = __ballot(dsc);
+        if (lane == 0) L.disc[r] = m;
     }
     __syncthreads();
+    // distance along the row to the nearest discontinuity within 16 columns:
+    // the lowest set bit at or right of the column, the highest at or left of it
     for (int k = tid; k < kFeatRegion * kFeatTile; k += 256) {
-        const int r = k / kFeatTile, c = k % kFeatTile;
-        int best = 17;
-        for (int dx = -kFeatHalo; dx <= kFeatHalo; ++dx)
-            if (L.disc[r][c + kFeatHalo + dx]) best = min(best, abs(dx));
-        L.g[r][c] = (uint8_t)best;
+        const int r = k / kFeatTile, pos = k % kFeatTile + kFeatHalo;
+        const unsigned long long m = L.disc[r];
+        const unsigned long long right = m >> pos, left = m << (63 - pos);
+        const int dr = right ? __builtin_ctzll(right) : 64, dl = left ? __builtin_clzll(left) : 64;
+        const int best = min(dl, dr);
+        L.g[r][k % kFeatTile] = (uint8_t)(best > kFeatHalo ? kFeatHalo + 1 : best);
     }
     __syncthreads();
     const int ti = tid % kFeatTile, tj = tid / kFeatTile;
@@ -80,22 +89,25 @@ __device__ inline bool tile_features(FeatLds &L, const float *__restrict__ depth
         const int gx = L.g[tj + kFeatHalo + dy][ti];
         d2 = min(d2, dy * dy + gx * gx);
     }
+    // pixel offsets scaled by 1/f (products with the reciprocals: equal to the
+    // quotients to an ulp)
+    const double ifx = 1.0 / fx, ify = 1.0 / fy;
     f[0] = D;
     f[2] = fminf(sqrtf((float)d2), 16.0f) / 16.0f;
-    f[3] = (float)(sqrt((i - cx) * (i - cx) + (j - cy) * (j - cy)) / fx);
+    f[3] = (float)(sqrt((i - cx) * (i - cx) + (j - cy) * (j - cy)) * ifx);
     if (i < 1 || j < 1 || i >= W - 1 || j >= H - 1) return false;
     const float Dl = L.dep[tj + kFeatHalo + 1][ti + kFeatHalo], Dr = L.dep[tj + kFeatHalo + 1][ti + kFeatHalo + 2];
     const float Du = L.dep[tj + kFeatHalo][ti + kFeatHalo + 1], Dd = L.dep[tj + kFeatHalo + 2][ti + kFeatHalo + 1];
     if (!(Dl > 0.0f && Dr > 0.0f && Du > 0.0f && Dd > 0.0f)) return false;
-    const double ax = (i + 1 - cx) / fx * Dr - (i - 1 - cx) / fx * Dl;
-    const double ay = (j - cy) / fy * Dr - (j - cy) / fy * Dl;
+    const double ax = (i + 1 - cx) * ifx * Dr - (i - 1 - cx) * ifx * Dl;
+    const double ay = (j - cy) * ify * Dr - (j - cy) * ify * Dl;
     const double az = (double)Dr - (double)Dl;
-    const double bx = (i - cx) / fx * Dd - (i - cx) / fx * Du;
-    const double by = (j + 1 - cy) / fy * Dd - (j - 1 - cy) / fy * Du;
+    const double bx = (i - cx) * ifx * Dd - (i - cx) * ifx * Du;
+    const double by = (j + 1 - cy) * ify * Dd - (j - 1 - cy) * ify * Du;
     const double bz = (double)Dd - (double)Du;
     const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
     const double nl = sqrt(nx * nx + ny * ny + nz * nz);
-    const double rx = (i - cx) / fx, ry = (j - cy) / fy;
+    const double rx = (i - cx) * ifx, ry = (j - cy) * ify;
     const double rl = sqrt(rx * rx + ry * ry + 1.0);
     if (!(nl > 0.0)) return false;
     f[1] = (float)(fabs(nx * rx + ny * ry + nz) / (nl * rl));
