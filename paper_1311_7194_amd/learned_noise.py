@@ -1,11 +1,17 @@
 """Learned measurement-noise experiment: train on fused-surface residuals,
 compare against the quadratic model on held-out sequences.
 
-Training data: each training sequence is fused with the quadratic noise
-model; then every sampled frame is raycast from its own pose and each pixel
-with a measurement, defined features and a hit gives (features, r = D - Z),
-the residual of the measurement against the fused surface.  The network is
-trained on these with the Gaussian NLL (GPU kernels, Adam).
+Training data: every sampled frame of a training sequence is compared with
+a surface fused (with the quadratic noise model) from frames that exclude
+it: the even frames are fused and the sampled odd frames raycast from their
+own poses, then the other way round ("leave_out").  Each pixel with a
+measurement, defined features and a hit gives (features, r = D - Z), the
+residual of the measurement against that surface, so the residual holds the
+sensor's noise and the fused surface's error but not the frame's own
+contribution to that surface.  The older target ("fused": every frame fused,
+then each sampled frame raycast against the surface it helped form) is kept
+for comparison.  The network is trained on these with the Gaussian NLL (GPU
+kernels, Adam).
 
 Evaluation on held-out sequences, each fused twice (quadratic and learned):
   nll        mean NLL of the held-out residuals (of the quadratic-fused
@@ -44,6 +50,7 @@ class ExperimentSize:
     batch: int = 65536
     lr: float = 1e-3
     eval_every: int = 10
+    residuals: str = "leave_out"   # or "fused"
 
 
 def full_size() -> ExperimentSize:
@@ -97,6 +104,31 @@ def collect(vol: Volume, spec, frames, every: int, collector: M.SampleCollector)
         d, p = frames[k]
         vol.raycast(spec.K, p, vert, nrm)
         collector.add(d, spec.K, p, vert)
+
+
+def collect_left_out(vol: Volume, spec, frames, every: int, collector: M.SampleCollector):
+    """Residuals of every `every`-th frame against the surface fused from the
+    frames of the other parity (the frame itself never contributes)."""
+    vert = torch.empty((spec.K.height, spec.K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(vert)
+    for parity in (0, 1):
+        fuse(vol, spec, [f for k, f in enumerate(frames) if k % 2 == parity])
+        for k in range(0, len(frames), every):
+            if k % 2 == parity:
+                continue
+            d, p = frames[k]
+            vol.raycast(spec.K, p, vert, nrm)
+            collector.add(d, spec.K, p, vert)
+
+
+def residual_samples(vol: Volume, spec, frames, every: int, collector: M.SampleCollector, mode: str):
+    if mode == "leave_out":
+        collect_left_out(vol, spec, frames, every, collector)
+    elif mode == "fused":
+        fuse(vol, spec, frames)
+        collect(vol, spec, frames, every, collector)
+    else:
+        raise ValueError(mode)
 
 
 def quadratic_logvar(x: torch.Tensor) -> torch.Tensor:
@@ -164,8 +196,7 @@ def run(size: ExperimentSize, seed: int = 0, log=print) -> dict:
     for s in size.train_seeds:
         spec = spec_for(s, size)
         frames = _frames(spec)
-        fuse(vol, spec, frames)
-        collect(vol, spec, frames, size.sample_every, collector)
+        residual_samples(vol, spec, frames, size.sample_every, collector, size.residuals)
         log(f"[learned] train seq {s}: {int(collector.count.item())} samples so far ({time.time() - t0:.0f} s)")
     x, r = collector.samples()
     trainer = M.NoiseTrainer(M.init_params(seed), lr=size.lr)
@@ -180,11 +211,12 @@ def run(size: ExperimentSize, seed: int = 0, log=print) -> dict:
     for s in size.test_seeds:
         spec = spec_for(s, size)
         frames = _frames(spec)
-        # quadratic fusion: residuals for the NLL, then surface metrics
-        fuse(vol, spec, frames)
+        # held-out residuals of the training target's kind for the NLL, then
+        # the quadratic fusion of the whole sequence for the surface metrics
         hc = M.SampleCollector(len(frames) // size.eval_every * per_frame + per_frame, size.width, size.height)
-        collect(vol, spec, frames, size.eval_every, hc)
+        residual_samples(vol, spec, frames, size.eval_every, hc, size.residuals)
         hx, hr = hc.samples()
+        fuse(vol, spec, frames)
         nll_q = nll(quadratic_logvar(hx), hr)
         nll_l = nll(M.forward(trainer.params, hx), hr)
         surf_q = surface_error(vol, spec, frames, size.eval_every)
@@ -204,7 +236,8 @@ def run(size: ExperimentSize, seed: int = 0, log=print) -> dict:
         return dict(mean=float(d.mean()), std=float(d.std(ddof=1)) if len(d) > 1 else 0.0,
                     learned_better=int((d < 0).sum()), n=len(d))
 
-    return dict(train_samples=int(x.shape[0]), train_steps=size.steps, train_seconds=train_s,
+    return dict(residuals=size.residuals, train_samples=int(x.shape[0]), train_steps=size.steps,
+                train_seconds=train_s,
                 first_loss=losses[0], final_loss=float(np.mean(losses[-20:])), quadratic_train_nll=quad_train,
                 heldout=rows, nll_diff=paired("nll_quadratic", "nll_learned"),
                 surface_diff_vox=paired("surface_quadratic_vox", "surface_learned_vox"),
@@ -221,10 +254,15 @@ def main():
     ap.add_argument("--size", choices=["small", "full"], default="small")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--train", type=int, default=0, help="use only the first N training sequences (0: all)")
+    ap.add_argument("--test", type=int, default=0, help="use only the first N held-out sequences (0: all)")
+    ap.add_argument("--residuals", choices=["leave_out", "fused"], default="leave_out")
     a = ap.parse_args()
     size = full_size() if a.size == "full" else small_size()
+    size.residuals = a.residuals
     if a.train:
         size.train_seeds = size.train_seeds[:a.train]
+    if a.test:
+        size.test_seeds = size.test_seeds[:a.test]
     res = run(size, a.seed, log=lambda m: print(m, file=sys.stderr, flush=True))
     res.pop("params")
     print(json.dumps(res), flush=True)
