@@ -434,10 +434,14 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     last = [f[1][min(warmup, len(f[1])) - 1] for f in frames]
     group, tune_ms = batch.autotune_raycast(last, reps=reps_tune)
     log(f"c5: batched raycast group {group} ({tune_ms * 1e3:.1f} us per batched raycast on the warm-up volumes)")
+    # fusion grid, timed on whole steps of the next warm-up frame (the volumes are reset before timing)
+    fuse_grid, fuse_tune_ms = batch.autotune_fuse(*step_args(min(warmup, n_steps - 1)), reps=reps_tune)
+    log(f"c5: batched fusion grid {fuse_grid} ({fuse_tune_ms:.3f} ms per step on a warm-up frame)")
 
-    def timed_batched(graph):
+    def timed_batched(graph, persistent=False):
         reset_all()
         batch.set_graph(graph)
+        batch.set_persistent(persistent)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for k in range(n_steps):
@@ -449,6 +453,9 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     ms_graph = timed_batched(True)
     stats_b = [v.stats() for v in vols]
     ms_nograph = timed_batched(False)
+    ms_persistent = timed_batched(False, persistent=True)
+    stats_pers = [v.stats() for v in vols]
+    batch.set_persistent(False)
     # 16 sequential plain runs on the same frames, same raycast group
     reset_all()
     for v in vols:
@@ -466,20 +473,24 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1)
     stats_p = [v.stats() for v in vols]
-    same = all(a[k] == b[k] for a, b in zip(stats_b, stats_p)
-               for k in ("total_updates", "total_new_blocks", "allocated_blocks", "total_candidates"))
+    keys_ = ("total_updates", "total_new_blocks", "allocated_blocks", "total_candidates")
+    same = all(a[k] == b[k] for a, b in zip(stats_b, stats_p) for k in keys_)
+    same_pers = all(a[k] == b[k] for a, b in zip(stats_pers, stats_p) for k in keys_)
     upd = sum(st["total_updates"] for st in stats_b)
     pixels = sum(len(f[0]) * s.K.width * s.K.height for f, s in zip(frames, specs))
     flags = [st["status_flags"] for st in stats_b]
     fill = max(st["allocated_blocks"] / s.grid.capacity_blocks for st, s in zip(stats_b, specs))
     res = dict(workload="c5-batch16", scenes=16, steps=n_steps, frames=sum(len(f[0]) for f in frames),
                updates=upd, pixels=pixels, status_flags=max(flags), max_pool_fill=fill, raycast_group=group,
-               batched_graph_ms=ms_graph, batched_nograph_ms=ms_nograph, sequential_plain_ms=ms_seq,
+               fuse_grid=fuse_grid,
+               batched_graph_ms=ms_graph, batched_nograph_ms=ms_nograph, batched_one_launch_ms=ms_persistent,
+               sequential_plain_ms=ms_seq,
                voxel_updates_per_s=upd / (ms_graph * 1e-3),
                sequential_voxel_updates_per_s=upd / (ms_seq * 1e-3),
                raycast_pixels_per_s_incl_fusion=pixels / (ms_graph * 1e-3),
                speedup_vs_sequential=ms_seq / ms_graph, speedup_graph_vs_nograph=ms_nograph / ms_graph,
-               counters_equal_to_sequential=same)
+               speedup_one_launch_vs_six=ms_nograph / ms_persistent,
+               counters_equal_to_sequential=same, one_launch_counters_equal_to_sequential=same_pers)
     del batch, vols
     torch.cuda.empty_cache()
     return res

@@ -6,7 +6,7 @@
  * allocation of Section 7.2) and raycasts each volume from the same pose
  * (Section 5), exactly as tsdf_integrate_frame followed by tsdf_raycast would,
  * but with six kernel launches that cover every scene instead of five per
- * scene.  The paper handles one sensor stream; batching is an addition for
+ * scene, or with one cooperative launch (tsdf_batch_set_persistent).  The paper handles one sensor stream; batching is an addition for
  * serving many small scenes at once, where per-scene launches would leave
  * most of the chip idle.  Results per scene are bitwise identical to the
  * single-volume calls.
@@ -51,6 +51,16 @@ void tsdf_batch_destroy(tsdf_batch *b);
  * needs a created (non-null) stream. */
 tsdf_status tsdf_batch_set_graph(tsdf_batch *b, int32_t enable);
 
+/* Persistent mode (enable != 0): the whole step runs as one cooperative
+ * launch of a resident grid (as many 256-thread workgroups as can be
+ * resident at once), its six phases separated by grid barriers; each phase
+ * uses the same kernel bodies and work decomposition as the six launches, so
+ * results are bitwise those of the default mode.  Graph capture does not
+ * apply to this mode (the step is one launch already).  TSDF_EINVAL for a
+ * batch of volumes without the dense block index.  A step returns TSDF_EHIP
+ * if the device cannot run the cooperative launch. */
+tsdf_status tsdf_batch_set_persistent(tsdf_batch *b, int32_t enable);
+
 /* Lanes per ray of the batched raycast (1, 2, 4, 8 or 16). */
 tsdf_status tsdf_batch_set_raycast_group(tsdf_batch *b, int32_t group);
 int32_t tsdf_batch_get_raycast_group(const tsdf_batch *b);
@@ -73,6 +83,23 @@ tsdf_status tsdf_batch_step(tsdf_batch *b, const float *const *depth_dev, const 
 tsdf_status tsdf_batch_autotune_raycast(tsdf_batch *b, const double *poses_c2w, float *const *vertex_dev,
                                         float *const *normal_dev, int32_t reps, hipStream_t stream,
                                         int32_t *best_group, float *best_ms);
+
+/* Workgroups of the batched fusion launch (1..65536; 2560 after creation):
+ * the fusion walks every scene's candidate blocks with this many persistent
+ * workgroups of four wavefronts.  Results do not depend on it. */
+tsdf_status tsdf_batch_set_fuse_grid(tsdf_batch *b, uint32_t workgroups);
+uint32_t tsdf_batch_get_fuse_grid(const tsdf_batch *b);
+
+/* Autotuner of the fusion grid: runs whole steps (six launches, one warm-up
+ * and `reps` timed per candidate) on the given frames with each candidate
+ * grid, keeps the fastest and reports it with the mean time of one step in
+ * milliseconds.  The frames are fused (6 + 6 reps) times into the volumes:
+ * tune on warm-up data and reset the volumes afterwards.  Arguments as
+ * tsdf_batch_step; synchronises `stream`. */
+tsdf_status tsdf_batch_autotune_fuse(tsdf_batch *b, const float *const *depth_dev, const double *poses_c2w,
+                                     float *const *vertex_dev, float *const *normal_dev,
+                                     const tsdf_noise_model *noise, int32_t reps, hipStream_t stream,
+                                     uint32_t *best_grid, float *best_ms);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,8 @@
 #include <new>
 #include <vector>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "fuse_device.h"
 #include "raycast_device.h"
 #include "tsdf_batch.h"
@@ -180,6 +182,115 @@ __global__ __launch_bounds__(256) void batch_raycast(const SceneDesc *__restrict
                                gt - (long long)d.ray_base * 64 * G);
 }
 
+// The whole step in one cooperative launch: the six phases above run one
+// after the other inside a resident grid (the launch fails, and nothing runs,
+// when the grid cannot be resident at once), separated by grid barriers.
+// Every phase is the same body over the same work decomposition as its
+// separate kernel, so the results are those of the six launches.  Every
+// workgroup reaches every barrier: no phase returns early.
+template <typename S, int G, bool kDense, bool kMlp>
+__global__ __launch_bounds__(256) void batch_persistent(const SceneDesc *__restrict__ sd, int n, uint32_t prep_total,
+                                                        uint32_t ray_total)
+{
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ uint32_t pre[kMaxScenes + 1];
+    __shared__ SpanLds L;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // frame reset
+    for (uint32_t s = blockIdx.x; s < (uint32_t)n; s += gridDim.x)
+        if (sd[s].active) frame_begin_body(sd[s].v.state, sd[s].v.ctr, tid);
+    grid.sync();
+    // pixel preparation: one 16x16 tile per workgroup and iteration
+    for (uint32_t w = blockIdx.x; w < prep_total; w += gridDim.x) {
+        const SceneDesc &d = sd[scene_of(sd, n, w, false)];
+        if (d.active) {   // uniform over the workgroup
+            const uint32_t local = w - d.prep_base;
+            prep_body<kMlp>(d.v, d.depth, d.cam, d.noise, (int)(local % (uint32_t)d.tiles_x16),
+                            (int)(local / (uint32_t)d.tiles_x16));
+        }
+        __syncthreads();   // the next tile reuses the preparation's LDS
+    }
+    grid.sync();
+    // block fusion over every scene's candidates, one wavefront per candidate
+    {
+        scene_prefix<false>(sd, n, pre);
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (tid >> 6));
+        const uint32_t nwaves = gridDim.x * 4u;
+        if (blockIdx.x == 0 && tid < n && sd[tid].active)
+            atomicAdd(&sd[tid].v.state->total_candidates, (unsigned long long)(pre[tid + 1] - pre[tid]));
+        FuseAcc acc;
+        int cur = -1;
+        for (uint32_t g = wave; g < pre[n]; g += nwaves) {
+            const int s = scene_at(pre, n, g);
+            if (s != cur) {
+                if (cur >= 0) fuse_flush(sd[cur].v, acc, wave, lane);
+                cur = s;
+            }
+            const SceneDesc &d = sd[s];
+            fuse_block<S>(d.v, d.cam, d.fc, d.v.cand_list[g - pre[s]], lane, acc);
+        }
+        if (cur >= 0) fuse_flush(sd[cur].v, acc, wave, lane);
+    }
+    grid.sync();
+    // span reset
+    for (long long gt = (long long)blockIdx.x * 256 + tid; gt < (long long)ray_total * 64;
+         gt += (long long)gridDim.x * 256) {
+        const uint32_t tile = (uint32_t)(gt >> 6);
+        const SceneDesc &d = sd[scene_of(sd, n, tile, true)];
+        if (d.active)
+            range_clear_body(d.v, d.tiles_x8, d.tiles_y8, d.cam.width, d.cam.height, gt - (long long)d.ray_base * 64);
+    }
+    grid.sync();
+    // range pass over every scene's blocks
+    {
+        span_lds_init(L);
+        scene_prefix<true>(sd, n, pre);   // (synchronises the workgroup)
+        for (uint32_t g = blockIdx.x * 256u + tid; g < pre[n]; g += gridDim.x * 256u) {
+            int s = 0;
+            for (int k = 1; k < n; ++k) s += pre[k] <= g ? 1 : 0;
+            const SceneDesc &d = sd[s];
+            range_block(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, g - pre[s],
+                        [&](uint32_t c, uint32_t zl, uint32_t zh) {
+                            if (!span_lds_add(L, ((uint32_t)s << 26) | c, zl, zh)) {
+                                uint32_t *cmin = d.v.pix_range;
+                                uint32_t *cmax = cmin + (size_t)((d.cam.width + kCell - 1) / kCell) *
+                                                            ((d.cam.height + kCell - 1) / kCell);
+                                atomicMin(&cmin[c], zl);
+                                atomicMax(&cmax[c], zh);
+                            }
+                        });
+        }
+        __syncthreads();
+        for (int e = tid; e < kSpanLds; e += 256) {
+            const uint32_t key = L.key[e];
+            if (key != kSpanEmpty) {
+                const SceneDesc &d = sd[key >> 26];
+                const uint32_t c = key & ((1u << 26) - 1u);
+                uint32_t *cmin = d.v.pix_range;
+                uint32_t *cmax =
+                    cmin + (size_t)((d.cam.width + kCell - 1) / kCell) * ((d.cam.height + kCell - 1) / kCell);
+                atomicMin(&cmin[c], L.lo[e]);
+                atomicMax(&cmax[c], L.hi[e]);
+            }
+        }
+    }
+    grid.sync();
+    // raycast: 256-thread chunks of the (tile, ray, lane) space; a wavefront's
+    // 64 threads lie in one tile, so the tests below are wave-uniform
+    const long long total = (long long)ray_total * 64 * G;
+    for (long long base = (long long)blockIdx.x * 256; base < total; base += (long long)gridDim.x * 256) {
+        const long long gt = base + tid;
+        const uint32_t tile = (uint32_t)(gt / (64 * G));
+        if (tile < ray_total) {
+            const int s = __builtin_amdgcn_readfirstlane(scene_of(sd, n, tile, true));
+            const SceneDesc &d = sd[s];
+            if (d.active)
+                raycast_body<S, G, kDense>(d.v, d.cam, d.stamp, d.tiles_x8, d.tiles_y8, d.vertex, d.normal,
+                                           gt - (long long)d.ray_base * 64 * G);
+        }
+    }
+}
+
 }  // namespace tsdf
 
 using namespace tsdf;
@@ -192,6 +303,10 @@ struct tsdf_batch {
     uint32_t prep_total, ray_total;
     int32_t storage, dense, group;
     bool use_graph;
+    bool persistent;     // one cooperative launch per step instead of six
+    uint32_t fuse_grid;  // workgroups of the persistent fusion launch
+    int32_t coop_grid;   // resident workgroups of the cooperative kernel last launched (0: not yet)
+    const void *coop_fn;
     hipGraphExec_t exec;
     int32_t graph_key;   // (noise kind, group) the graph was captured for; -1 = none
 };
@@ -232,6 +347,48 @@ static hipError_t enqueue_raycast(tsdf_batch *b, hipStream_t s)
     return hipGetLastError();
 }
 
+// The step as one cooperative launch of batch_persistent, its grid the number
+// of workgroups that can be resident at once (occupancy x CUs).
+template <typename S, int G, bool kMlp>
+static hipError_t launch_persistent_t(tsdf_batch *b, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&batch_persistent<S, G, true, kMlp>);
+    if (b->coop_fn != fn) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        if (per_cu <= 0 || cus <= 0) return hipErrorInvalidConfiguration;
+        b->coop_grid = per_cu * cus;
+        b->coop_fn = fn;
+    }
+    const SceneDesc *sd = b->dev;
+    int n = (int)b->vols.size();
+    uint32_t pt = b->prep_total, rt = b->ray_total;
+    void *args[] = {(void *)&sd, (void *)&n, (void *)&pt, (void *)&rt};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)b->coop_grid), dim3(256), args, 0, s);
+}
+
+template <typename S, bool kMlp>
+static hipError_t launch_persistent_g(tsdf_batch *b, hipStream_t s)
+{
+    switch (b->group) {
+    case 1: return launch_persistent_t<S, 1, kMlp>(b, s);
+    case 2: return launch_persistent_t<S, 2, kMlp>(b, s);
+    case 4: return launch_persistent_t<S, 4, kMlp>(b, s);
+    case 16: return launch_persistent_t<S, 16, kMlp>(b, s);
+    default: return launch_persistent_t<S, 8, kMlp>(b, s);
+    }
+}
+
+static hipError_t enqueue_persistent(tsdf_batch *b, int32_t noise_kind, hipStream_t s)
+{
+    const bool mlp = noise_kind == TSDF_NOISE_MLP;
+    if (b->storage == TSDF_F16) return mlp ? launch_persistent_g<__half, true>(b, s) : launch_persistent_g<__half, false>(b, s);
+    return mlp ? launch_persistent_g<float, true>(b, s) : launch_persistent_g<float, false>(b, s);
+}
+
 static hipError_t enqueue_step(tsdf_batch *b, int32_t noise_kind, hipStream_t s)
 {
     const int n = (int)b->vols.size();
@@ -241,9 +398,9 @@ static hipError_t enqueue_step(tsdf_batch *b, int32_t noise_kind, hipStream_t s)
     else
         hipLaunchKernelGGL(batch_prep<false>, dim3(b->prep_total), dim3(256), 0, s, b->dev, n);
     if (b->storage == TSDF_F16)
-        hipLaunchKernelGGL(batch_fuse<__half>, dim3(kFuseGrid), dim3(256), 0, s, b->dev, n);
+        hipLaunchKernelGGL(batch_fuse<__half>, dim3(b->fuse_grid), dim3(256), 0, s, b->dev, n);
     else
-        hipLaunchKernelGGL(batch_fuse<float>, dim3(kFuseGrid), dim3(256), 0, s, b->dev, n);
+        hipLaunchKernelGGL(batch_fuse<float>, dim3(b->fuse_grid), dim3(256), 0, s, b->dev, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return enqueue_raycast(b, s);
@@ -319,6 +476,10 @@ tsdf_status tsdf_batch_create(tsdf_volume *const *vols, const tsdf_intrinsics *K
     b->host.assign(n, SceneDesc());
     b->prep_total = b->ray_total = 0;
     b->use_graph = false;
+    b->persistent = false;
+    b->fuse_grid = kFuseGrid;
+    b->coop_grid = 0;
+    b->coop_fn = nullptr;
     b->exec = nullptr;
     b->graph_key = -1;
     b->group = 8;
@@ -380,6 +541,13 @@ tsdf_status tsdf_batch_set_graph(tsdf_batch *b, int32_t enable)
     return TSDF_OK;
 }
 
+tsdf_status tsdf_batch_set_persistent(tsdf_batch *b, int32_t enable)
+{
+    if (!b || (enable && !b->dense)) return TSDF_EINVAL;
+    b->persistent = enable != 0;
+    return TSDF_OK;
+}
+
 tsdf_status tsdf_batch_set_raycast_group(tsdf_batch *b, int32_t group)
 {
     if (!b || !(group == 1 || group == 2 || group == 4 || group == 8 || group == 16)) return TSDF_EINVAL;
@@ -401,8 +569,9 @@ tsdf_status tsdf_batch_step(tsdf_batch *b, const float *const *depth_dev, const 
     if (b->use_graph && !stream) return TSDF_EINVAL;   // capture needs a created stream
     tsdf_status st = stage_step(b, depth_dev, poses_c2w, vertex_dev, normal_dev, noise, stream);
     if (st != TSDF_OK) return st;
+    if (b->persistent) return enqueue_persistent(b, kind, stream) == hipSuccess ? TSDF_OK : TSDF_EHIP;
     if (!b->use_graph) return enqueue_step(b, kind, stream) == hipSuccess ? TSDF_OK : TSDF_EHIP;
-    const int32_t key = kind * 64 + b->group;
+    const int32_t key = (kind * 64 + b->group) * 65536 + (int32_t)b->fuse_grid;
     if (!b->exec || b->graph_key != key) {
         if (b->exec) {
             hipGraphExecDestroy(b->exec);
@@ -425,6 +594,63 @@ tsdf_status tsdf_batch_step(tsdf_batch *b, const float *const *depth_dev, const 
         b->graph_key = key;
     }
     return hipGraphLaunch(b->exec, stream) == hipSuccess ? TSDF_OK : TSDF_EHIP;
+}
+
+tsdf_status tsdf_batch_set_fuse_grid(tsdf_batch *b, uint32_t workgroups)
+{
+    if (!b || workgroups < 1 || workgroups > 65536) return TSDF_EINVAL;
+    b->fuse_grid = workgroups;
+    return TSDF_OK;
+}
+
+uint32_t tsdf_batch_get_fuse_grid(const tsdf_batch *b) { return b ? b->fuse_grid : 0; }
+
+tsdf_status tsdf_batch_autotune_fuse(tsdf_batch *b, const float *const *depth_dev, const double *poses_c2w,
+                                     float *const *vertex_dev, float *const *normal_dev,
+                                     const tsdf_noise_model *noise, int32_t reps, hipStream_t stream,
+                                     uint32_t *best_grid, float *best_ms)
+{
+    if (!b || !depth_dev || !poses_c2w || !vertex_dev || !normal_dev || reps < 1 || !best_grid || !best_ms)
+        return TSDF_EINVAL;
+    const int32_t kind = noise ? noise->kind : TSDF_NOISE_QUADRATIC;
+    if (kind != TSDF_NOISE_QUADRATIC && kind != TSDF_NOISE_CONSTANT && kind != TSDF_NOISE_MLP) return TSDF_EINVAL;
+    if (kind == TSDF_NOISE_MLP && !noise->mlp_params_dev) return TSDF_EINVAL;
+    // persistent fusion grids: one, two and four rounds of resident waves
+    // (five per SIMD on 256 CUs), and two rounds at half and double width
+    const uint32_t candidates[5] = {1280, 1920, 2560, 3840, 5120};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return TSDF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return TSDF_EHIP;
+    }
+    tsdf_status st = TSDF_OK;
+    float best = 3.4e38f;
+    uint32_t bestg = b->fuse_grid;
+    for (int c = 0; c < 5 && st == TSDF_OK; ++c) {
+        b->fuse_grid = candidates[c];
+        st = stage_step(b, depth_dev, poses_c2w, vertex_dev, normal_dev, noise, stream);
+        if (st == TSDF_OK && enqueue_step(b, kind, stream) != hipSuccess) st = TSDF_EHIP;   // warm-up
+        if (st == TSDF_OK && hipEventRecord(e0, stream) != hipSuccess) st = TSDF_EHIP;
+        for (int r = 0; r < reps && st == TSDF_OK; ++r) {
+            st = stage_step(b, depth_dev, poses_c2w, vertex_dev, normal_dev, noise, stream);
+            if (st == TSDF_OK && enqueue_step(b, kind, stream) != hipSuccess) st = TSDF_EHIP;
+        }
+        float ms = 0.0f;
+        if (st == TSDF_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = TSDF_EHIP;
+        if (st == TSDF_OK && ms / reps < best) {
+            best = ms / reps;
+            bestg = candidates[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->fuse_grid = bestg;
+    *best_grid = bestg;
+    *best_ms = best;
+    return st;
 }
 
 tsdf_status tsdf_batch_autotune_raycast(tsdf_batch *b, const double *poses_c2w, float *const *vertex_dev,

@@ -35,7 +35,8 @@ EXPORTED = [
     "tsdf_batch_set_raycast_group", "tsdf_batch_get_raycast_group", "tsdf_batch_step",
     "tsdf_batch_autotune_raycast", "tsdf_icp_workspace_bytes", "tsdf_icp_step", "tsdf_icp_run",
     "tsdf_set_update_rule", "tsdf_evict_workspace_bytes", "tsdf_evict_blocks", "tsdf_icp_run_noalloc",
-    "tsdf_mesh_case", "tsdf_mesh_workspace_bytes", "tsdf_extract_mesh",
+    "tsdf_mesh_case", "tsdf_mesh_workspace_bytes", "tsdf_extract_mesh", "tsdf_batch_set_persistent",
+    "tsdf_batch_set_fuse_grid", "tsdf_batch_get_fuse_grid", "tsdf_batch_autotune_fuse",
 ]
 
 
@@ -124,6 +125,11 @@ def lib():
         L.tsdf_batch_destroy.argtypes = [P]
         L.tsdf_batch_destroy.restype = None
         L.tsdf_batch_set_graph.argtypes = [P, ctypes.c_int32]
+        L.tsdf_batch_set_persistent.argtypes = [P, ctypes.c_int32]
+        L.tsdf_batch_set_fuse_grid.argtypes = [P, ctypes.c_uint32]
+        L.tsdf_batch_get_fuse_grid.argtypes = [P]
+        L.tsdf_batch_get_fuse_grid.restype = ctypes.c_uint32
+        L.tsdf_batch_autotune_fuse.argtypes = [P, P, P, P, P, P, ctypes.c_int32, P, P, P]
         L.tsdf_batch_set_raycast_group.argtypes = [P, ctypes.c_int32]
         L.tsdf_batch_get_raycast_group.argtypes = [P]
         L.tsdf_batch_step.argtypes = [P, P, P, P, P, P, P]
@@ -139,7 +145,8 @@ def lib():
         L.tsdf_extract_mesh.argtypes = [P, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P, P]
         for name in EXPORTED:
             if name not in ("tsdf_destroy_volume", "tsdf_status_string", "tsdf_batch_bytes", "tsdf_batch_destroy",
-                            "tsdf_icp_workspace_bytes", "tsdf_evict_workspace_bytes", "tsdf_mesh_workspace_bytes"):
+                            "tsdf_icp_workspace_bytes", "tsdf_evict_workspace_bytes", "tsdf_mesh_workspace_bytes",
+                            "tsdf_batch_get_fuse_grid"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -417,6 +424,10 @@ class Batch:
     def set_graph(self, enable: bool):
         _check(lib().tsdf_batch_set_graph(self.handle, 1 if enable else 0), "tsdf_batch_set_graph")
 
+    def set_persistent(self, enable: bool):
+        """One cooperative launch per step instead of six (tsdf_batch.h)."""
+        _check(lib().tsdf_batch_set_persistent(self.handle, 1 if enable else 0), "tsdf_batch_set_persistent")
+
     def set_raycast_group(self, group: int):
         _check(lib().tsdf_batch_set_raycast_group(self.handle, int(group)), "tsdf_batch_set_raycast_group")
 
@@ -465,6 +476,37 @@ class Batch:
         _check(lib().tsdf_batch_autotune_raycast(self.handle, pa.ctypes.data_as(ctypes.c_void_p), self._vp,
                                                  self._np, int(reps), stream_handle(stream), ctypes.byref(best),
                                                  ctypes.byref(ms)), "tsdf_batch_autotune_raycast")
+        return int(best.value), float(ms.value)
+
+
+    def set_fuse_grid(self, workgroups: int):
+        _check(lib().tsdf_batch_set_fuse_grid(self.handle, ctypes.c_uint32(int(workgroups))), "tsdf_batch_set_fuse_grid")
+
+    @property
+    def fuse_grid(self) -> int:
+        return int(lib().tsdf_batch_get_fuse_grid(self.handle))
+
+    def autotune_fuse(self, depths: Sequence[Optional[torch.Tensor]], poses, noise_kind: int = NOISE_QUADRATIC,
+                      coeff: float = 0.0015, mlp_params: Optional[torch.Tensor] = None, reps: int = 2, stream=None):
+        """Picks the fusion grid by timing whole steps on these frames (which
+        get fused into the volumes repeatedly: reset them afterwards)."""
+        n = len(self.volumes)
+        dp = (ctypes.c_void_p * n)()
+        for k, d in enumerate(depths):
+            if d is not None:
+                assert d.is_cuda and d.dtype == torch.float32 and d.is_contiguous()
+                dp[k] = d.data_ptr()
+        pa = self._poses(poses)
+        nm = NoiseModel(int(noise_kind), float(coeff),
+                        ctypes.c_void_p(mlp_params.data_ptr()) if mlp_params is not None else None)
+        best = ctypes.c_uint32(0)
+        ms = ctypes.c_float(0)
+        if stream is None:
+            stream = self.stream
+            stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().tsdf_batch_autotune_fuse(self.handle, dp, pa.ctypes.data_as(ctypes.c_void_p), self._vp,
+                                              self._np, ctypes.byref(nm), int(reps), stream_handle(stream),
+                                              ctypes.byref(best), ctypes.byref(ms)), "tsdf_batch_autotune_fuse")
         return int(best.value), float(ms.value)
 
 

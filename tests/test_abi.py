@@ -215,3 +215,8 @@ def test_mesh_host_validation_without_volume(lib):
     assert lib.tsdf_mesh_workspace_bytes(None) == 0
     fake = ctypes.c_void_p(0x1000)   # never dereferenced: the call returns first
     assert lib.tsdf_extract_mesh(None, fake, fake, None, 1, fake, 1 << 20, fake, None) == T.EINVAL
+
+
+def test_batch_persistent_validation(lib):
+    assert lib.tsdf_batch_set_persistent(None, 1) == T.EINVAL
+    assert lib.tsdf_batch_set_persistent(None, 0) == T.EINVAL

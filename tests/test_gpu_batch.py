@@ -50,15 +50,19 @@ STAT_KEYS = ("allocated_blocks", "total_updates", "total_fresh_updates", "total_
 RULES = {0: {}, 1: dict(w=0.2), 2: dict(weight_kind=1, w_max=60000.0)}   # Algorithms 3, 1, 2
 
 
-@pytest.mark.parametrize("noise,graph,storage,dense,group,rule", [
-    ("quadratic", True, 0, True, 4, 0),
-    ("constant", False, 0, False, 8, 0),
-    ("quadratic", True, 1, True, 1, 0),
-    ("mlp", True, 0, True, 16, 0),
-    ("quadratic", True, 0, True, 4, 1),
-    ("quadratic", False, 1, True, 8, 2),
+@pytest.mark.parametrize("noise,graph,storage,dense,group,rule,persistent", [
+    ("quadratic", True, 0, True, 4, 0, False),
+    ("constant", False, 0, False, 8, 0, False),
+    ("quadratic", True, 1, True, 1, 0, False),
+    ("mlp", True, 0, True, 16, 0, False),
+    ("quadratic", True, 0, True, 4, 1, False),
+    ("quadratic", False, 1, True, 8, 2, False),
+    # the single cooperative launch
+    ("quadratic", False, 0, True, 4, 0, True),
+    ("mlp", False, 0, True, 2, 0, True),
+    ("quadratic", False, 1, True, 8, 2, True),
 ])
-def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group, rule):
+def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group, rule, persistent):
     specs = scenes()
     kind = dict(quadratic=tsdf.NOISE_QUADRATIC, constant=tsdf.NOISE_CONSTANT, mlp=tsdf.NOISE_MLP)[noise]
     coeff = 0.05 if noise == "constant" else 0.0015
@@ -75,12 +79,14 @@ def test_batch_equals_plain(tsdf, noise, graph, storage, dense, group, rule):
     batched = [mk(s) for s in specs]
     plain = [mk(s) for s in specs]
     b = tsdf.Batch(batched, [s.K for s in specs], graph=graph)
+    b.set_persistent(persistent)
     b.set_raycast_group(group)
     for v in plain:
         v.set_raycast_group(group)
     steps = max(s.n_frames for s in specs)
     for t in range(steps):
-        print(f"[batch] {noise} graph={graph} storage={storage} dense={dense} G={group} rule={rule} step {t}",
+        print(f"[batch] {noise} graph={graph} storage={storage} dense={dense} G={group} rule={rule} "
+              f"persistent={persistent} step {t}",
               flush=True)
         depths, poses = [], []
         for s in specs:
@@ -166,3 +172,42 @@ def test_batch_autotune_and_rejections(tsdf):
     bad[1][0][0] = 2.0
     with pytest.raises(tsdf.TsdfError):
         b.step(depths, bad)
+
+
+def test_fuse_grid_autotune_keeps_results(tsdf):
+    # the fusion grid changes how candidates are spread over workgroups, not
+    # the result: a batch tuned on warm-up frames, then reset, must end
+    # bitwise equal to a batch with the default grid
+    specs = scenes()
+    frames = []
+    for s in specs:
+        frames.append([sequence_frame(s, t) for t in range(s.n_frames)])
+    ends = []
+    for tune in (False, True):
+        vols = [gpu_volume_for(s) for s in specs]
+        b = tsdf.Batch(vols, [s.K for s in specs], graph=True)
+        if tune:
+            d0 = [f[0][0].cuda().contiguous() for f in frames]
+            p0 = [f[0][1] for f in frames]
+            grid, ms = b.autotune_fuse(d0, p0, reps=1)
+            torch.cuda.synchronize()
+            print(f"[batch] fusion grid {grid} ({ms:.3f} ms per step)", flush=True)
+            assert grid in (1280, 1920, 2560, 3840, 5120) and b.fuse_grid == grid and ms > 0
+            for v in vols:
+                v.reset()
+            b.set_fuse_grid(1280 if grid != 1280 else 5120)   # a grid other than the default
+        for t in range(max(s.n_frames for s in specs)):
+            depths = [f[t][0].cuda().contiguous() if t < len(f) else None for f in frames]
+            poses = [f[t][1] if t < len(f) else None for f in frames]
+            b.step(depths, poses)
+        torch.cuda.synchronize()
+        ends.append(([sorted_export(v) for v in vols], [x.clone() for x in b.vertex],
+                     [{k: v.stats()[k] for k in STAT_KEYS} for v in vols]))
+    (ea, va, sa), (eb, vb, sb) = ends
+    assert sa == sb
+    for x, y in zip(ea, eb):
+        assert np.array_equal(x[0], y[0]) and torch.equal(x[1], y[1]) and torch.equal(x[2], y[2])
+    for x, y in zip(va, vb):
+        assert torch.equal(x, y)
+    with pytest.raises(tsdf.TsdfError):
+        b.set_fuse_grid(0)
