@@ -390,7 +390,7 @@ def roofline_of(res):
     # replay, the maps alone (a lower bound)
     per_launch = res.get("raycast_bytes", 32 * res["width"] * res["height"])
     achieved = per_launch / (res["raycast_avg_us"] * 1e-6) / 1e9
-    t = profiled_traffic("raycast_kernel", f"{res['workload']}/{res['storage']}")
+    t = profiled_traffic(f"raycast_kernel/G{res['raycast_group']}", f"{res['workload']}/{res['storage']}")
     return dict(kernel="raycast_kernel", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 5), traffic=t,
                 bytes_per_launch=int(per_launch), avg_launch_us=round(res["raycast_avg_us"], 2),
