@@ -83,6 +83,11 @@ __device__ __forceinline__ void prep_body(const VolumeView &v, const float *__re
     const bool in_image = i < cam.width && j < cam.height;
     float D = in_image ? depth[(size_t)j * cam.width + i] : 0.0f;
     const bool valid = in_image && D > 0.0f && isfinite(D);
+    // a tile without a valid pixel (background) only clears its pixel map
+    if (!__syncthreads_or(valid)) {
+        if (in_image) v.pixmap[(size_t)j * cam.width + i] = make_float2(0.0f, 0.0f);
+        return;
+    }
     const float inv_delta_f = (float)v.inv_delta;
     float ph = valid ? measurement_variance(noise, D, inv_delta_f) : 0.0f;
     PrepCandLds *cand;
