@@ -125,38 +125,38 @@ __global__ __launch_bounds__(128) void train_kernel(const uint16_t *__restrict__
         }
     __syncthreads();
 
-    // dW2[o][i] = sum_m e2[m][o] h1[m][i]: M = o, N = i, K = samples (8 per step)
+    // dW2[o][i] = sum_m e2[m][o] h1[m][i]: M = o, N = i, K = samples (16 per step)
     f32x16_t w2c;
     {
-        const int kh = 4 * (lane >> 5);
+        const int kh = 8 * (lane >> 5);
         f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            bf16x4_t a, b;
+        for (int kk = 0; kk < 4; ++kk) {
+            i16x8_t a, b;
 #pragma unroll
-            for (int el = 0; el < 4; ++el) {
-                a[el] = (short)S.e2[wv][8 * kk + kh + el][col];
-                b[el] = (short)S.wave[wv].h1[8 * kk + kh + el][col];
+            for (int el = 0; el < 8; ++el) {
+                a[el] = (short)S.e2[wv][16 * kk + kh + el][col];
+                b[el] = (short)S.wave[wv].h1[16 * kk + kh + el][col];
             }
-            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+            c = mfma_bf16_k16(a, b, c);
         }
         w2c = c;
     }
     // dh1[m][i] = sum_o e2[m][o] W2[o][i]: M = samples (two tiles), N = i, K = o
     {
-        const int kh = 4 * (lane >> 5);
+        const int kh = 8 * (lane >> 5);
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                bf16x4_t a, b;
+            for (int kk = 0; kk < 2; ++kk) {
+                i16x8_t a, b;
 #pragma unroll
-                for (int el = 0; el < 4; ++el) {
-                    a[el] = (short)S.e2[wv][32 * t + col][8 * kk + kh + el];
-                    b[el] = (short)params[MLP_W2 + (8 * kk + kh + el) * kMlpHidden + col];
+                for (int el = 0; el < 8; ++el) {
+                    a[el] = (short)S.e2[wv][32 * t + col][16 * kk + kh + el];
+                    b[el] = (short)params[MLP_W2 + (16 * kk + kh + el) * kMlpHidden + col];
                 }
-                c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+                c = mfma_bf16_k16(a, b, c);
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {

@@ -7,7 +7,7 @@
 // a depth discontinuity (capped at 16 px) and radial pixel distance / fx.
 // Weights are bfloat16, accumulation float32; layer-1 and layer-2 inputs are
 // rounded to bfloat16 (round to nearest even).  Layer 2 runs on the matrix
-// cores (v_mfma_f32_32x32x8_bf16), one wavefront = 64 samples = two 32-row
+// cores (v_mfma_f32_32x32x16_bf16), one wavefront = 64 samples = two 32-row
 // tiles.
 #pragma once
 
@@ -22,8 +22,19 @@ constexpr int kMlpParamsPadded = 1256;
 enum { MLP_W1 = 0, MLP_B1 = 128, MLP_W2 = 160, MLP_B2 = 1184, MLP_W3 = 1216, MLP_B3 = 1248 };
 constexpr int kEdgeCap = 16;
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef short i16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+// D += A B on the matrix cores, v_mfma_f32_32x32x16_bf16 (A 32x16, B 16x32,
+// D 32x32, bf16 in, fp32 accumulate).  Lane l supplies A[l % 32][8 (l / 32) + e]
+// and B[8 (l / 32) + e][l % 32] for e = 0..7 (bf16 bit patterns) and holds
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r.
+__device__ __forceinline__ f32x16_t mfma_bf16_k16(i16x8_t a, i16x8_t b, f32x16_t c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                    c, 0, 0, 0);
+}
 
 // bfloat16 round to nearest even (finite inputs), as the bit pattern and as a value
 __device__ __forceinline__ uint16_t bf16_bits(float f)
@@ -63,27 +74,25 @@ struct MlpWaveLds {
 };
 
 // Layer 2 for the 64 samples of a wavefront on the matrix cores:
-// acc[tile] = h1[32 tile rows][32] x W2^T[32][32] (bf16 in, fp32 out).
-// Operand layout of v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32):
-// lane l supplies A[l % 32][4 (l / 32) + 0..3] and B[4 (l / 32) + 0..3][l % 32];
-// it receives D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator r.
+// acc[tile] = h1[32 tile rows][32] x W2^T[32][32] (bf16 in, fp32 out), two
+// K = 16 steps per tile.
 __device__ __forceinline__ void mlp_layer2_mfma(const MlpWaveLds &w, const uint16_t *__restrict__ W2bits, int lane,
                                                 f32x16_t acc[2])
 {
-    const int col = lane & 31, kh = 4 * (lane >> 5);
+    const int col = lane & 31, kh = 8 * (lane >> 5);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < kMlpHidden / 8; ++kk) {
-            bf16x4_t a, b;
+        for (int kk = 0; kk < kMlpHidden / 16; ++kk) {
+            i16x8_t a, b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                a[e] = (short)w.h1[32 * t + col][8 * kk + kh + e];
+            for (int e = 0; e < 8; ++e) {
+                a[e] = (short)w.h1[32 * t + col][16 * kk + kh + e];
                 // B[k][n] = W2[n][k]: output unit n = col, input k
-                b[e] = (short)W2bits[col * kMlpHidden + 8 * kk + kh + e];
+                b[e] = (short)W2bits[col * kMlpHidden + 16 * kk + kh + e];
             }
-            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+            c = mfma_bf16_k16(a, b, c);
         }
         acc[t] = c;
     }
@@ -151,20 +160,20 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpParamsLds &P, const uin
         w.h[lane][o] = bf16_bits(silu(a));
     }
     __syncthreads();
-    const int col = lane & 31, kh = 4 * (lane >> 5);
+    const int col = lane & 31, kh = 8 * (lane >> 5), rh = 4 * (lane >> 5);
     f32x16_t acc[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < kMlpHidden / 8; ++kk) {
-            bf16x4_t a, b;
+        for (int kk = 0; kk < kMlpHidden / 16; ++kk) {
+            i16x8_t a, b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                a[e] = (short)w.h[32 * t + col][8 * kk + kh + e];
-                b[e] = (short)params[MLP_W2 + col * kMlpHidden + 8 * kk + kh + e];
+            for (int e = 0; e < 8; ++e) {
+                a[e] = (short)w.h[32 * t + col][16 * kk + kh + e];
+                b[e] = (short)params[MLP_W2 + col * kMlpHidden + 16 * kk + kh + e];
             }
-            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+            c = mfma_bf16_k16(a, b, c);
         }
         acc[t] = c;
     }
@@ -174,25 +183,25 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpParamsLds &P, const uin
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            w.h[32 * t + 8 * (r >> 2) + kh + (r & 3)][col] = bf16_bits(silu(acc[t][r] + b2));
+            w.h[32 * t + 8 * (r >> 2) + rh + (r & 3)][col] = bf16_bits(silu(acc[t][r] + b2));
     __syncthreads();
     // s[m] = b3 + sum_o h2[m][o] W3[o]: M = samples, N = 1 (column 0 of B), K = o
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         f32x16_t c = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < kMlpHidden / 8; ++kk) {
-            bf16x4_t a, b;
+        for (int kk = 0; kk < kMlpHidden / 16; ++kk) {
+            i16x8_t a, b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                a[e] = (short)w.h[32 * t + col][8 * kk + kh + e];
-                b[e] = col == 0 ? (short)params[MLP_W3 + 8 * kk + kh + e] : (short)0;
+            for (int e = 0; e < 8; ++e) {
+                a[e] = (short)w.h[32 * t + col][16 * kk + kh + e];
+                b[e] = col == 0 ? (short)params[MLP_W3 + 16 * kk + kh + e] : (short)0;
             }
-            c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+            c = mfma_bf16_k16(a, b, c);
         }
         if (col == 0) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) w.out[32 * t + 8 * (r >> 2) + kh + (r & 3)] = c[r] + P.p[MLP_B3];
+            for (int r = 0; r < 16; ++r) w.out[32 * t + 8 * (r >> 2) + rh + (r & 3)] = c[r] + P.p[MLP_B3];
         }
     }
     __syncthreads();
