@@ -397,11 +397,14 @@ def roofline_of(res):
                 blocks_read_per_launch=round(res.get("raycast_blocks_read", 0.0), 1))
 
 
-def run_batch_c5(steps=None, warmup=3, reps_tune=3):
+def run_batch_c5(steps=None, warmup=40, reps_tune=3):
     """The 16-scene batch: step k fuses and raycasts frame k of every scene
     that still has one, as one graph-captured batched step, timed against
     the same frames run scene after scene through the single-volume calls
-    (and against the batched step without the graph)."""
+    (and against the batched step without the graph).  The autotuners run
+    after `warmup` untimed steps (a third of the longest sequence), on
+    volumes as full as those of the middle of the timed run; the timed run
+    starts again from empty volumes."""
     from paper_1311_7194_amd import Batch, Volume
     from synthetic.configs import config_c5
 
@@ -434,6 +437,9 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     last = [f[1][min(warmup, len(f[1])) - 1] for f in frames]
     group, tune_ms = batch.autotune_raycast(last, reps=reps_tune)
     log(f"c5: batched raycast group {group} ({tune_ms * 1e3:.1f} us per batched raycast on the warm-up volumes)")
+    # the sequential runs get each scene's own best group, tuned on the same volumes
+    seq_groups = [v.autotune_raycast(s.K, p)[0] for v, s, p in zip(vols, specs, last)]
+    log(f"c5: single-volume raycast groups {seq_groups}")
     # fusion grid, timed on whole steps of the next warm-up frame (the volumes are reset before timing)
     fuse_grid, fuse_tune_ms = batch.autotune_fuse(*step_args(min(warmup, n_steps - 1)), reps=reps_tune)
     log(f"c5: batched fusion grid {fuse_grid} ({fuse_tune_ms:.3f} ms per step on a warm-up frame)")
@@ -456,10 +462,10 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     ms_persistent = timed_batched(False, persistent=True)
     stats_pers = [v.stats() for v in vols]
     batch.set_persistent(False)
-    # 16 sequential plain runs on the same frames, same raycast group
+    # 16 sequential plain runs on the same frames, each with its own tuned raycast group
     reset_all()
-    for v in vols:
-        v.set_raycast_group(group)
+    for v, g in zip(vols, seq_groups):
+        v.set_raycast_group(g)
     vert = [torch.empty((s.K.height, s.K.width, 4), dtype=torch.float32, device="cuda") for s in specs]
     nrm = [torch.empty_like(x) for x in vert]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -482,7 +488,7 @@ def run_batch_c5(steps=None, warmup=3, reps_tune=3):
     fill = max(st["allocated_blocks"] / s.grid.capacity_blocks for st, s in zip(stats_b, specs))
     res = dict(workload="c5-batch16", scenes=16, steps=n_steps, frames=sum(len(f[0]) for f in frames),
                updates=upd, pixels=pixels, status_flags=max(flags), max_pool_fill=fill, raycast_group=group,
-               fuse_grid=fuse_grid,
+               sequential_raycast_groups=seq_groups, fuse_grid=fuse_grid,
                batched_graph_ms=ms_graph, batched_nograph_ms=ms_nograph, batched_one_launch_ms=ms_persistent,
                sequential_plain_ms=ms_seq,
                voxel_updates_per_s=upd / (ms_graph * 1e-3),
