@@ -18,6 +18,30 @@ def Kvec(K):
     return (K.fx, K.fy, K.cx, K.cy)
 
 
+FP16_U = 2.0 ** -11   # unit roundoff of FP16 (round to nearest)
+
+
+def fp16_bounds(n):
+    """Bounds on |dT_hat| and |dP_hat| / P_hat of FP16 storage after at most
+    n updates of a voxel (one per frame), against exact arithmetic; the FP32
+    form's own error (below 1e-5) is added by the caller.
+
+    Each update reads the stored values, computes in FP32 and stores again.
+    - P_hat: storing rounds by at most FP16_U relative.  Algorithm 3 maps a
+      relative error e of P (P + Q keeps it) to (1 - K) e in K p_k, so the
+      errors add up to at most n FP16_U (the first store included).
+    - T_hat: T_hat lies in [-1, 1], where a store rounds by at most 2^-12
+      absolutely.  T + K (T_k - T) takes an error of T as (1 - K) times
+      itself, and an error e of P changes K by at most K (1 - K) e <= e / 4,
+      which moves T by at most 2 e / 4 (|T_k - T| <= 2).  Update m therefore
+      adds at most 2^-12 + m FP16_U / 2 = 2^-12 (1 + m), and n updates at most
+      2^-12 (n + n (n + 1) / 2).
+    """
+    t = 2.0 ** -12 * (n + n * (n + 1) / 2.0)
+    p = n * FP16_U
+    return t, p
+
+
 def gpu_blocks(vol):
     keys, T, P = vol.export()
     torch.cuda.synchronize()

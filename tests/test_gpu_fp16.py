@@ -1,11 +1,13 @@
 """FP16 storage against the FP64 oracle and the FP32 form (needs an MI355X).
 
 T_hat and P_hat stored in FP16 cannot meet the 1e-5 bound of the FP32 form
-(one rounding is up to 2^-11 relative), so these checks are reported with
-bounds derived from that rounding: the block set and the chi status of every
-voxel must still be exact (neither depends on stored values), |dT_hat| stays
-within a few hundred FP16 roundings of T_hat in [-1, 1] after a sequence of
-updates, |dP_hat| / P_hat within 2 %, and the raycast depth within 0.1 voxel.
+(one rounding is up to 2^-11 relative), so these checks use bounds derived
+from that rounding (tests.parity.fp16_bounds, for one update per frame): the
+block set and the chi status of every voxel must still be exact (neither
+depends on stored values), |dT_hat| and |dP_hat| / P_hat within the derived
+bounds plus the FP32 form's 1e-5, and the raycast depth within 0.1 voxel (a
+T_hat error e moves the crossing by about e delta / cos(incidence), delta =
+4 voxels; 0.1 voxel leaves room down to grazing incidence).
 """
 
 import numpy as np
@@ -13,7 +15,7 @@ import pytest
 import torch
 
 from synthetic.configs import sequence_frame, small_orbit
-from tests.parity import Kvec, camera_depth, gpu_blocks, gpu_volume_for, oracle_volume_for
+from tests.parity import Kvec, camera_depth, fp16_bounds, gpu_blocks, gpu_volume_for, oracle_volume_for
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -56,10 +58,12 @@ def test_fp16_storage_error(tsdf):
     assert np.array_equal(k16, ko) and np.array_equal(k32, ko)
     s64 = stats((T16, P16), (To, Po), "fp64-oracle")
     s32 = stats((T16, P16), (T32, P32), "fp32")
+    t_bound, p_bound = fp16_bounds(spec.n_frames)
+    print(f"[fp16] derived bounds after {spec.n_frames} updates: |dT| {t_bound:.3g}, |dP|/P {p_bound:.3g}", flush=True)
     for s in (s64, s32):
         assert s["chi_mismatch"] == 0
-        assert s["max_dT"] <= 2e-2 and s["rms_dT"] <= 2e-3
-        assert s["max_rel_dP"] <= 2e-2
+        assert s["max_dT"] <= t_bound + 1e-5
+        assert s["max_rel_dP"] <= p_bound + 1e-5
     # raycast depth against the oracle's
     _, pose = sequence_frame(spec, 3)
     v16, n16 = g16.raycast(spec.K, pose)
