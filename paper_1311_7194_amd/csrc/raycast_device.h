@@ -589,14 +589,36 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         float Fs[6];
 #pragma unroll
         for (int e = 0; e < 6; ++e) Fs[e] = kNaN;
-        // sample e in {+x, -x, +y, -y, +z, -z} is taken by lane e % G of the group
+        // sample e in {+x, -x, +y, -y, +z, -z} is taken by lane e % G of the
+        // group.  A lane taking several samples gives each its own copy of the
+        // slot cache (the march's, refilled where the stencil leaves its
+        // block), so their index and voxel loads are all in flight together.
+        constexpr int kPer = (6 + G - 1) / G;
+        int nc[kPer][3];
+        float nf[kPer][3];
+        bool nin[kPer];
+        SlotCache ncache[kPer];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            if (hit && (e % G) == j) {
+        for (int t = 0; t < kPer; ++t) {
+            const int e = j + t * G;
+            nin[t] = hit && e < 6;
+            if (nin[t]) {
                 double qe[3] = {qh[0], qh[1], qh[2]};
                 qe[e >> 1] += (e & 1) ? -1.0 : 1.0;
-                float Fv;
-                if (sample_q<S, kDense>(v, cache, qe, Fv)) Fs[e] = Fv;
+                nin[t] = stencil(v, qe, nc[t], nf[t]);
+            }
+            ncache[t] = cache;
+            if (nin[t] && ((nc[t][0] >> 3) != cache.B[0] || (nc[t][1] >> 3) != cache.B[1] ||
+                           (nc[t][2] >> 3) != cache.B[2]))
+                fill_cache<kDense>(v, ncache[t], nc[t][0] >> 3, nc[t][1] >> 3, nc[t][2] >> 3);
+        }
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            float Fv;
+            if (nin[t] && interp_cached<S>(v, ncache[t], nc[t], nf[t], Fv)) {
+#pragma unroll
+                for (int e = 0; e < 6; ++e)
+                    if (e == j + t * G) Fs[e] = Fv;
             }
         }
 #pragma unroll
