@@ -82,6 +82,10 @@ def fuse_bytes(st, elem, pixels):
     return (4 * elem * upd_old + 2 * 512 * elem * st["total_new_blocks"] + 8 * pixels + 4 * st["total_candidates"])
 
 
+# lanes per ray of the single-volume raycast: 0 = autotuned per workload, else fixed (--raycast-group)
+RAYCAST_GROUP = 0
+
+
 def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=None, rule=None):
     """noise: None (quadratic) or bf16 MLP parameters (learned variance).
     frames: pre-generated (depths, poses) to reuse.
@@ -101,8 +105,13 @@ def run_sequence(spec, storage, steps, warmup, q_hat=1e-4, noise=None, frames=No
         vol.integrate(depths[k], K, poses[k], kind, 0.0015, noise)
         vol.raycast(K, poses[k], vert, nrm)
     torch.cuda.synchronize()
-    group, tune_ms = vol.autotune_raycast(K, poses[max(warmup - 1, 0)])
-    log(f"{spec.name}: raycast group size {group} ({tune_ms * 1e3:.1f} us on the warm-up volume)")
+    if RAYCAST_GROUP:
+        group = RAYCAST_GROUP
+        vol.set_raycast_group(group)
+        log(f"{spec.name}: raycast group size {group} (fixed)")
+    else:
+        group, tune_ms = vol.autotune_raycast(K, poses[max(warmup - 1, 0)])
+        log(f"{spec.name}: raycast group size {group} ({tune_ms * 1e3:.1f} us on the warm-up volume)")
     vol.reset()
     vol.set_timing(True)
     vol.read_timing(reset=True)
@@ -600,10 +609,15 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=0, help="limit the batched steps (0: all 120)")
     ap.add_argument("--icp-iters", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--raycast-group", type=int, default=0, choices=[0, 1, 2, 4, 8, 16],
+                    help="lanes per ray of the single-volume raycast (0: autotuned); a fixed value makes "
+                         "profiler runs, whose counters perturb the autotuner's timings, time the same kernel")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size reference "
                          "dispatch for the profiler's byte counters)")
     args = ap.parse_args()
+    global RAYCAST_GROUP
+    RAYCAST_GROUP = args.raycast_group
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
