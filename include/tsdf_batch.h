@@ -6,10 +6,10 @@
  * allocation of Section 7.2) and raycasts each volume from the same pose
  * (Section 5), exactly as tsdf_integrate_frame followed by tsdf_raycast would,
  * but with six kernel launches that cover every scene instead of five per
- * scene, or with one cooperative launch (tsdf_batch_set_persistent).  The paper handles one sensor stream; batching is an addition for
- * serving many small scenes at once, where per-scene launches would leave
- * most of the chip idle.  Results per scene are bitwise identical to the
- * single-volume calls.
+ * scene, or with one cooperative launch (tsdf_batch_set_persistent).  The
+ * paper handles one sensor stream; batching is an addition for serving many
+ * small scenes at once, where per-scene launches would leave most of the chip
+ * idle.  Results per scene are bitwise identical to the single-volume calls.
  *
  * The step can be captured into a hipGraph once and replayed; per-step inputs
  * travel in a small device table (tsdf_batch_bytes, caller-owned) that each
@@ -93,8 +93,8 @@ uint32_t tsdf_batch_get_fuse_grid(const tsdf_batch *b);
 /* Autotuner of the fusion grid: runs whole steps (six launches, one warm-up
  * and `reps` timed per candidate) on the given frames with each candidate
  * grid, keeps the fastest and reports it with the mean time of one step in
- * milliseconds.  The frames are fused (6 + 6 reps) times into the volumes:
- * tune on warm-up data and reset the volumes afterwards.  Arguments as
+ * milliseconds.  The frames are fused 5 (1 + reps) times into the volumes
+ * (five candidates): tune on warm-up data and reset the volumes afterwards.  Arguments as
  * tsdf_batch_step; synchronises `stream`. */
 tsdf_status tsdf_batch_autotune_fuse(tsdf_batch *b, const float *const *depth_dev, const double *poses_c2w,
                                      float *const *vertex_dev, float *const *normal_dev,

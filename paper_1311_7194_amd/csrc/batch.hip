@@ -615,8 +615,8 @@ tsdf_status tsdf_batch_autotune_fuse(tsdf_batch *b, const float *const *depth_de
     const int32_t kind = noise ? noise->kind : TSDF_NOISE_QUADRATIC;
     if (kind != TSDF_NOISE_QUADRATIC && kind != TSDF_NOISE_CONSTANT && kind != TSDF_NOISE_MLP) return TSDF_EINVAL;
     if (kind == TSDF_NOISE_MLP && !noise->mlp_params_dev) return TSDF_EINVAL;
-    // persistent fusion grids: one, two and four rounds of resident waves
-    // (five per SIMD on 256 CUs), and two rounds at half and double width
+    // persistent fusion grids of 1, 1.5, 2, 3 and 4 rounds of resident waves
+    // (five per SIMD on 256 CUs: 1280 workgroups of four wavefronts a round)
     const uint32_t candidates[5] = {1280, 1920, 2560, 3840, 5120};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return TSDF_EHIP;
