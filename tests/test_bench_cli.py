@@ -30,3 +30,11 @@ def test_no_gpu_is_an_error_not_a_fallback():
     rc, out = run_bench("--steps", "1", "--warmup", "0")
     assert rc == 1
     assert json.loads(out[-1]) == {"error": "no GPU visible"}
+
+
+def test_raycast_group_takes_only_the_built_group_sizes():
+    # the raycast kernels are instantiated for 1, 2, 4, 8 and 16 lanes per ray
+    rc, _ = run_bench("--raycast-group", "3")
+    assert rc == 2
+    rc, _ = run_bench("--gpus", "2", "--raycast-group", "8")
+    assert rc == 2   # parsed, then refused for the GPU count
