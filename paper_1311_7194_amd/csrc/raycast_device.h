@@ -234,40 +234,6 @@ __device__ __forceinline__ void fill_cache(const VolumeView &v, SlotCache &c, in
     c.positive = pos;
 }
 
-// The march's refill, without control flow around the cache: only the
-// index loads are conditional on `need`, the cache takes the new entries by
-// selection (a loop-carried cache updated inside a branch is copied on every
-// iteration).  Dense index only.
-__device__ __forceinline__ void refill_dense(const VolumeView &v, SlotCache &c, bool need, int bx, int by, int bz)
-{
-    const uint32_t n0 = (uint32_t)v.nblk[0], n01 = n0 * (uint32_t)v.nblk[1];
-    const uint32_t lin = (uint32_t)block_linear(v, bx, by, bz);
-    const bool inx = bx + 1 < v.nblk[0], iny = by + 1 < v.nblk[1], inz = bz + 1 < v.nblk[2];
-    int32_t raw[8];
-    if (need) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
-            raw[k] = v.block_index[lin + (in ? (k & 1) + ((k & 2) ? n0 : 0u) + ((k & 4) ? n01 : 0u) : 0u)];
-        }
-    }
-    const uint32_t chi_base = v.capacity * (uint32_t)kBlockVoxels;
-    bool pos = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const bool in = (!(k & 1) || inx) && (!(k & 2) || iny) && (!(k & 4) || inz);
-        const int32_t e = in ? raw[k] : -1;
-        pos &= (e < 0) || (e & kIndexPositive);
-        const uint32_t b = e < 0 ? chi_base : (uint32_t)(e & kIndexSlotMask) * (uint32_t)kBlockVoxels;
-        c.base[k] = need ? b : c.base[k];
-        if (k == 0) c.empty = need ? e < 0 : c.empty;
-    }
-    c.positive = need ? pos : c.positive;
-    c.B[0] = need ? bx : c.B[0];
-    c.B[1] = need ? by : c.B[1];
-    c.B[2] = need ? bz : c.B[2];
-}
-
 // Trilinear F at integer base c (global voxel indices) with fractions f,
 // using offsets from the cache (c must lie in cell c.B).  False when invalid.
 template <typename S>
@@ -462,11 +428,7 @@ __device__ __forceinline__ void raycast_body(const VolumeView &v, const Camera &
         const bool inside = stencil(v, q, c, f) && !done && n <= n_end;
         const int b0 = c[0] >> 3, b1 = c[1] >> 3, b2 = c[2] >> 3;
         const bool need = inside && (b0 != cache.B[0] || b1 != cache.B[1] || b2 != cache.B[2]);
-        if constexpr (kDense) {
-            refill_dense(v, cache, need, b0, b1, b2);
-        } else {
-            if (need) fill_cache<kDense>(v, cache, b0, b1, b2);
-        }
+        if (need) fill_cache<kDense>(v, cache, b0, b1, b2);
         if constexpr (kMark) {
             if (need && !cache.empty) {
                 const uint64_t lb = block_linear(v, b0, b1, b2);
