@@ -27,7 +27,7 @@ __device__ __forceinline__ void frame_begin_body(DeviceState *st, Counters *ctr,
 constexpr int kTile = 16;             // 16x16 pixels per workgroup
 constexpr int kLdsSet = 2048;         // LDS hash set of block keys
 constexpr int kLdsList = 1024;        // unique keys held for the global pass
-constexpr int kSubRanges = 4;         // depth sub-intervals of a pixel's frustum cell
+constexpr int kSubRanges = 2;         // depth sub-intervals of a pixel's frustum cell
 
 // Marks `key` as a candidate of this frame; the first marker appends it to
 // the candidate list.  Used, one lane at a time, for keys that did not fit
@@ -123,28 +123,31 @@ __device__ __forceinline__ void prep_body(const VolumeView &v, const float *__re
         const double z0 = fmax((double)D - v.delta, 0.0), z1 = (double)D + v.delta;
         const double ul = (i - 0.5 - cam.cx) / cam.fx, uh = (i + 0.5 - cam.cx) / cam.fx;
         const double vl = (j - 0.5 - cam.cy) / cam.fy, vh = (j + 0.5 - cam.cy) / cam.fy;
+        // A slice [za, zb] is spanned by the points z * d + t, d the rotated
+        // direction of a point of the pixel square at unit depth: as z > 0,
+        // its box per axis is the span of z * [dmin, dmax] over the two depths,
+        // [dmin, dmax] the range of d (separable in the square's two sides).
+        // Kept in grid units; the pad of 1 % of a voxel covers the rounding.
         const double pad = 0.01 * v.vs;
+        double emin[3], emax[3], cmin[3], cmax[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double r0 = cam.R[3 * a], r1 = cam.R[3 * a + 1], r2 = cam.R[3 * a + 2];
+            const double p0 = r0 * ul, p1 = r0 * uh, q0 = r1 * vl, q1 = r1 * vh;
+            emin[a] = (fmin(p0, p1) + fmin(q0, q1) + r2) * v.inv_vs;
+            emax[a] = (fmax(p0, p1) + fmax(q0, q1) + r2) * v.inv_vs;
+            cmin[a] = (cam.t[a] - pad - v.origin[a]) * v.inv_vs - 0.5;
+            cmax[a] = (cam.t[a] + pad - v.origin[a]) * v.inv_vs - 0.5;
+        }
         for (int sr = 0; sr < kSubRanges; ++sr) {
             const double za = z0 + (z1 - z0) * sr / kSubRanges;
             const double zb = (sr == kSubRanges - 1) ? z1 : z0 + (z1 - z0) * (sr + 1) / kSubRanges;
-            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const double z = (k & 4) ? zb : za;
-                const double xc = ((k & 1) ? uh : ul) * z, yc = ((k & 2) ? vh : vl) * z;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const double xw = cam.R[3 * a] * xc + cam.R[3 * a + 1] * yc + cam.R[3 * a + 2] * z + cam.t[a];
-                    lo[a] = fmin(lo[a], xw);
-                    hi[a] = fmax(hi[a], xw);
-                }
-            }
             int b0[3], b1[3];
             bool empty = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                double g0 = ceil((lo[a] - pad - v.origin[a]) * v.inv_vs - 0.5);
-                double g1 = floor((hi[a] + pad - v.origin[a]) * v.inv_vs - 0.5);
+                double g0 = ceil(fmin(za * emin[a], zb * emin[a]) + cmin[a]);
+                double g1 = floor(fmax(za * emax[a], zb * emax[a]) + cmax[a]);
                 g0 = fmax(g0, 0.0);
                 g1 = fmin(g1, (double)(v.dims[a] - 1));
                 empty |= !(g0 <= g1);
