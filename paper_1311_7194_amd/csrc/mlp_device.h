@@ -64,7 +64,16 @@ struct MlpParamsLds {
 __device__ __forceinline__ void mlp_stage_params(MlpParamsLds &s, const uint16_t *__restrict__ params, int tid,
                                                  int nthreads)
 {
-    for (int k = tid; k < kMlpParams; k += nthreads) s.p[k] = bf16_value(params[k]);
+    // eight loads per thread in flight before their LDS stores (clamped
+    // indices keep them in bounds)
+    for (int k0 = tid; k0 < kMlpParams; k0 += 8 * nthreads) {
+        uint16_t b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) b[q] = params[min(k0 + q * nthreads, kMlpParams - 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (k0 + q * nthreads < kMlpParams) s.p[k0 + q * nthreads] = bf16_value(b[q]);
+    }
 }
 
 // Per-wavefront LDS scratch for the layer-2 operands and the output reduction.

@@ -25,7 +25,8 @@ constexpr int kFeatRegion = kFeatTile + 2 * kFeatHalo;   // 48 (discontinuity re
 constexpr int kFeatDepth = kFeatRegion + 2;              // 50 (depth incl. the neighbour ring)
 
 struct FeatLds {
-    float dep[kFeatDepth][kFeatDepth + 1];   // NaN = outside the image, 0 = no measurement
+    float dep[kFeatDepth + 2][kFeatDepth + 1];   // NaN = outside the image, 0 = no measurement; the last
+                                                 // two rows take the staging loop's partial round
     unsigned long long disc[kFeatRegion];    // discontinuities of each region row, bit c = column c
     uint8_t g[kFeatRegion][kFeatTile];       // row distance to the nearest discontinuity (17 = none)
 };
@@ -36,36 +37,58 @@ __device__ inline bool tile_features(FeatLds &L, const float *__restrict__ depth
                                      double cx, double cy, int i0, int j0, int tid, float f[4])
 {
     const float kOut = __uint_as_float(0x7fc00000u);   // quiet NaN: outside the image
-    for (int k = tid; k < kFeatDepth * kFeatDepth; k += 256) {
+    // every load of the thread is issued before the first LDS store (one
+    // memory round trip, not one per element); the index is clamped into the
+    // image so that each load is in bounds, and the value replaced outside it
+    constexpr int kN = kFeatDepth * kFeatDepth, kPer = (kN + 255) / 256;
+    static_assert(kPer * 256 <= (kFeatDepth + 2) * kFeatDepth, "the padding rows take the partial round");
+    float d[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = min(tid + 256 * q, kN - 1);
         const int r = k / kFeatDepth, c = k % kFeatDepth;
         const int jj = j0 - kFeatHalo - 1 + r, ii = i0 - kFeatHalo - 1 + c;
-        float d = kOut;
-        if (ii >= 0 && jj >= 0 && ii < W && jj < H) {
-            d = depth[(size_t)jj * W + ii];
-            if (!(d > 0.0f) || !isfinite(d)) d = 0.0f;
-        }
-        L.dep[r][c] = d;
+        d[q] = depth[(size_t)min(max(jj, 0), H - 1) * W + min(max(ii, 0), W - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = tid + 256 * q;   // below kPer * 256 <= (kFeatDepth + 2) * kFeatDepth
+        const int r = k / kFeatDepth, c = k % kFeatDepth;
+        const int jj = j0 - kFeatHalo - 1 + r, ii = i0 - kFeatHalo - 1 + c;
+        float x = d[q];
+        if (!(x > 0.0f) || !isfinite(x)) x = 0.0f;
+        L.dep[r][c] = (ii >= 0 && jj >= 0 && ii < W && jj < H) ? x : kOut;
     }
     __syncthreads();
     // discontinuity bits: wavefront w takes rows w, w + 4, ..., lane c < 48 one
     // column, and the row's ballot is its bit mask
+    // (the tests are combined with non-short-circuit operators, so that a row
+    // is straight-line code; lanes 48..63 read an in-bounds column and drop it)
     const int lane = tid & 63;
-    for (int r = tid >> 6; r < kFeatRegion; r += 4) {
-        bool dsc = false;
-        if (lane < kFeatRegion) {
-            const int c = lane;
-            const float D = L.dep[r + 1][c + 1];
-            if (D > 0.0f) {   // false for NaN and 0
-                const float nb[4] = {L.dep[r + 1][c + 2], L.dep[r + 1][c], L.dep[r + 2][c + 1], L.dep[r][c + 1]};
+    const int cl = min(lane, kFeatRegion - 1);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (isnan(nb[q])) continue;   // outside the image: does not count
-                    if (!(nb[q] > 0.0f) || fabs((double)nb[q] - (double)D) > 0.05 * (double)D) dsc = true;
-                }
-            }
+    for (int r0 = 0; r0 < kFeatRegion; r0 += 12) {
+        const int r = r0 + 3 * (tid >> 6);
+        float D[3], nb[3][4];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            D[e] = L.dep[r + e + 1][cl + 1];
+            nb[e][0] = L.dep[r + e + 1][cl + 2];
+            nb[e][1] = L.dep[r + e + 1][cl];
+            nb[e][2] = L.dep[r + e + 2][cl + 1];
+            nb[e][3] = L.dep[r + e][cl + 1];
         }
-        const unsigned long long m = __ballot(dsc);
-        if (lane == 0) L.disc[r] = m;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double Dd = (double)D[e], thr = 0.05 * Dd;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)   // a neighbour outside the image (NaN) does not count
+                any |= !isnan(nb[e][q]) & (!(nb[e][q] > 0.0f) | (fabs((double)nb[e][q] - Dd) > thr));
+            const bool dsc = (lane < kFeatRegion) & (D[e] > 0.0f) & any;   // D > 0 is false for NaN and 0
+            const unsigned long long m = __ballot(dsc);
+            if (lane == 0) L.disc[r + e] = m;
+        }
     }
     __syncthreads();
     // distance along the row to the nearest discontinuity within 16 columns:
