@@ -36,13 +36,10 @@ __device__ __forceinline__ f32x16_t mfma_bf16_k16(i16x8_t a, i16x8_t b, f32x16_t
                                                     c, 0, 0, 0);
 }
 
-// bfloat16 round to nearest even (finite inputs), as the bit pattern and as a value
-__device__ __forceinline__ uint16_t bf16_bits(float f)
-{
-    uint32_t b = __float_as_uint(f);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
+// bfloat16 round to nearest even, as the bit pattern and as a value: the
+// hardware conversion, which for every finite input gives the bits of adding
+// 0x7fff plus the kept lowest bit and truncating
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float((uint32_t)bf16_bits(f) << 16); }
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
