@@ -402,6 +402,11 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
     S *__restrict__ poolP = (S *)v.poolP;
     int bx, by, bz;
     unpack_key(key, bx, by, bz);
+    // The decisions run at a raised wave priority, the memory-bound rest of
+    // the block at the normal one: a SIMD then issues the arithmetic of the
+    // waves that are deciding ahead of the waves that wait on T and P (about
+    // 2 % faster than one priority throughout).
+    __builtin_amdgcn_s_setprio(2);
     // first probe of the block's hash chain, issued before the decisions so
     // that its latency overlaps them (only this wavefront inserts this key)
     unsigned long long first_entry = 0;
@@ -486,7 +491,10 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
         atomicAnd(&v.cand_bits[b >> 5], ~(1u << (b & 31)));
     }
     const unsigned long long any = __ballot(vmask != 0);
-    if (!any) return;
+    if (!any) {
+        __builtin_amdgcn_s_setprio(0);
+        return;
+    }
 
     int32_t slot = -1;
     int fresh = 0;
@@ -504,6 +512,7 @@ __device__ __forceinline__ void fuse_block(const VolumeView &v, const Camera &ca
     }
     slot = __shfl(slot, 0);
     fresh = __shfl(fresh, 0);
+    __builtin_amdgcn_s_setprio(0);
     if (slot < 0) return;
     // the block's bound and box as they stand, loaded ahead of the voxel data
     uint32_t old_min = kKeyPosInf, old_box = 0;
