@@ -60,6 +60,34 @@ def test_features_match_oracle(mlp):
     np.testing.assert_allclose(g[ov, 1], of[ov, 1], atol=1e-6)
 
 
+@pytest.mark.parametrize("W,H", [(37, 29), (200, 5), (5, 70), (33, 17)])
+def test_features_ragged_images_with_invalid_pixels(mlp, W, H):
+    """Images smaller than or ragged against the 16x16 tiles, so that the
+    48x48 feature window leaves the image on every side, with a depth step
+    (discontinuities) and scattered invalid readings (0, negative, NaN,
+    infinity) up to the borders."""
+    from synthetic.scenes import Intrinsics
+
+    rng = np.random.default_rng(1000 * W + H)
+    jj, ii = np.mgrid[0:H, 0:W]
+    d = (0.8 + 0.002 * ii + 0.003 * jj).astype(np.float32)
+    d[:, W // 2:] += np.float32(0.1)
+    bad = rng.random((H, W)) < 0.08
+    d[bad] = np.array([0.0, -1.0, np.nan, np.inf], np.float32)[rng.integers(0, 4, int(bad.sum()))]
+    K = Intrinsics(0.9 * W + 20.0, 0.9 * W + 20.0, W / 2.0 - 0.3, H / 2.0 + 0.2, W, H)
+    feat, valid = mlp.features(torch.from_numpy(d).cuda(), K)
+    torch.cuda.synchronize()
+    of, ov = oracle.mlp_features(d, Kvec(K))
+    g = feat.cpu().numpy().astype(np.float64)
+    gv = valid.cpu().numpy().astype(bool)
+    assert np.array_equal(gv, ov)
+    print(f"[mlp] {W}x{H}: valid features {int(ov.sum())} of {ov.size}", flush=True)
+    np.testing.assert_array_equal(g[:, 0], of[:, 0])
+    np.testing.assert_allclose(g[:, 2], of[:, 2], atol=1e-7)
+    np.testing.assert_allclose(g[:, 3], of[:, 3], rtol=1e-6)
+    np.testing.assert_allclose(g[ov, 1], of[ov, 1], atol=1e-6)
+
+
 def test_forward_matches_oracle(mlp):
     spec, d, pose = frame_depth()
     of, ov = oracle.mlp_features(d.numpy(), Kvec(spec.K))
