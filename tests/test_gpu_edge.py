@@ -2,8 +2,10 @@
 
 Frames without a single valid measurement, frames of one pixel and ragged
 sizes, a camera inside an allocated block (the near-plane path of the
-raycast), and exhaustion of the block pool and of the per-frame candidate
-list (sticky flags, TSDF_EFULL, recovery by reset).
+raycast), a wide truncation band seen from close by and at grazing angles
+(candidate boxes reaching the camera and crossing the grid's faces), and
+exhaustion of the block pool and of the per-frame candidate list (sticky
+flags, TSDF_EFULL, recovery by reset).
 """
 
 import numpy as np
@@ -100,6 +102,33 @@ def test_camera_inside_an_allocated_block(tsdf):
     rs = compare_raycast(vert.cpu().numpy(), nrm.cpu().numpy(), ovv, onn, ofl, pose, vs)
     print("[edge] camera inside a block", rs, flush=True)
     assert rs["hits"] > 100
+
+
+def test_wide_band_near_and_grazing_views(tsdf):
+    """A truncation band of 12 voxels seen from 2 cm in front of the sphere
+    (frustum cells reaching back to the camera, D - delta < 0), from outside
+    the grid at a grazing angle (cells crossing the grid's faces) and from a
+    corner: the candidate boxes must still hold every block that receives a
+    value, so the block sets and values equal the oracle's."""
+    import dataclasses
+
+    spec = config_c1(noise=False)
+    spec = dataclasses.replace(spec, grid=dataclasses.replace(spec.grid, trunc_voxels=12.0))
+    K = Intrinsics(55.0, 55.0, 31.7, 23.4, 64, 48)
+    views = [look_at((0.0, 0.0, 0.68), (0.0, 0.0, 1.0), up=(0.0, -1.0, 0.0)),
+             look_at((0.6, 0.05, 1.0), (-1.0, 0.0, 1.1)),
+             look_at((0.3, 0.3, 0.62), (-0.1, -0.05, 1.1))]
+    gv = gpu_volume_for(spec, max_wh=(64, 48))
+    ov = oracle_volume_for(spec)
+    for p in views:
+        d = render_depth(spec.scene, K, p).float()
+        ost = ov.integrate(d.numpy(), Kvec(K), p)
+        gv.integrate(d.cuda(), K, p)
+        st = gv.stats()
+        assert st["frame_updates"] == ost["updates"] and st["frame_new_blocks"] == ost["new_blocks"]
+        print("[edge] wide band view:", ost["updates"], "updates,", ost["new_blocks"], "new blocks", flush=True)
+        assert ost["updates"] > 0
+    compare_volumes(gv, ov)
 
 
 def test_pool_exhaustion_is_sticky_until_reset(tsdf):
