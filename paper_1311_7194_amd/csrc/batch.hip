@@ -167,11 +167,12 @@ __global__ __launch_bounds__(256) void batch_range(const SceneDesc *__restrict__
 }
 
 // One thread per (tile, ray, lane of the ray's group); wavefronts never
-// straddle tiles (64 G threads per tile), hence never scenes.
+// straddle tiles (64 G threads per tile), hence never scenes.  One wavefront
+// per workgroup, as in the single-volume raycast.
 template <typename S, int G, bool kDense>
-__global__ __launch_bounds__(256) void batch_raycast(const SceneDesc *__restrict__ sd, int n, uint32_t total_tiles)
+__global__ __launch_bounds__(64) void batch_raycast(const SceneDesc *__restrict__ sd, int n, uint32_t total_tiles)
 {
-    const long long gt = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long gt = (long long)blockIdx.x * 64 + threadIdx.x;
     const uint32_t tile = (uint32_t)(gt / (64 * G));
     if (tile >= total_tiles) return;
     // 64 G consecutive threads share a tile, so the scene is wave-uniform
@@ -321,11 +322,11 @@ template <typename S, bool kDense>
 static void launch_batch_raycast(int G, dim3 grid, hipStream_t s, const SceneDesc *sd, int n, uint32_t tiles)
 {
     switch (G) {
-    case 1: hipLaunchKernelGGL((batch_raycast<S, 1, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
-    case 2: hipLaunchKernelGGL((batch_raycast<S, 2, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
-    case 4: hipLaunchKernelGGL((batch_raycast<S, 4, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
-    case 16: hipLaunchKernelGGL((batch_raycast<S, 16, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
-    default: hipLaunchKernelGGL((batch_raycast<S, 8, kDense>), grid, dim3(256), 0, s, sd, n, tiles); break;
+    case 1: hipLaunchKernelGGL((batch_raycast<S, 1, kDense>), grid, dim3(64), 0, s, sd, n, tiles); break;
+    case 2: hipLaunchKernelGGL((batch_raycast<S, 2, kDense>), grid, dim3(64), 0, s, sd, n, tiles); break;
+    case 4: hipLaunchKernelGGL((batch_raycast<S, 4, kDense>), grid, dim3(64), 0, s, sd, n, tiles); break;
+    case 16: hipLaunchKernelGGL((batch_raycast<S, 16, kDense>), grid, dim3(64), 0, s, sd, n, tiles); break;
+    default: hipLaunchKernelGGL((batch_raycast<S, 8, kDense>), grid, dim3(64), 0, s, sd, n, tiles); break;
     }
 }
 
@@ -336,7 +337,7 @@ static hipError_t enqueue_raycast(tsdf_batch *b, hipStream_t s)
                        b->ray_total);
     hipLaunchKernelGGL(batch_range, dim3(2048), dim3(256), 0, s, b->dev, n);
     const long long threads = (long long)b->ray_total * 64 * b->group;
-    dim3 grid((unsigned)((threads + 255) / 256));
+    dim3 grid((unsigned)((threads + 63) / 64));
     if (b->storage == TSDF_F16) {
         if (b->dense) launch_batch_raycast<__half, true>(b->group, grid, s, b->dev, n, b->ray_total);
         else launch_batch_raycast<__half, false>(b->group, grid, s, b->dev, n, b->ray_total);
